@@ -1,0 +1,102 @@
+"""Negative controls: copies of the oracle with one planted mistake each,
+built on the CPU, must fail at least one of the pins that the real oracle
+passes. This shows the pins can detect the kind of slip they guard against.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import build as obuild
+from oracle import mini
+from oracle.ref import Oracle
+from tests import pins
+
+SRC = open(obuild.SRC).read()
+
+MUTANTS = {
+    # every site updated in each pass (no checkerboard): not the Ising chain
+    "no_checkerboard": ("if (((i + j) & 1u) != c) continue;", "(void)0;"),
+    # wrong sign of the energy change
+    "energy_sign": ("double dE = 2.0 * s * (J * n + h);", "double dE = -2.0 * s * (J * n + h);"),
+    # field term dropped
+    "field_dropped": ("double dE = 2.0 * s * (J * n + h);", "double dE = 2.0 * s * (J * n);"),
+    # left neighbour counted twice, right one never
+    "wrong_neighbour": ("s[(size_t)i * L + rt];", "s[(size_t)i * L + lf];"),
+    # bond sum counts the right neighbour twice and misses the lower one
+    "bond_sum": ("b += (int64_t)(me * (right + down));", "b += (int64_t)(me * (right + right));"),
+    # Philox key words swapped in the round
+    "philox_key": ("^ x1 ^ k0;", "^ x1 ^ k1;"),
+    # colour order reversed (a valid chain, but not the frozen one)
+    "colour_order": ("oracle_half_sweep(L, thr, seed, t, 0, s);\n        oracle_half_sweep(L, thr, seed, t, 1, s);",
+                     "oracle_half_sweep(L, thr, seed, t, 1, s);\n        oracle_half_sweep(L, thr, seed, t, 0, s);"),
+    # initial state uses the wrong comparison
+    "init_compare": ("s[(size_t)i * L + j] = ((uint64_t)u < pthr)", "s[(size_t)i * L + j] = ((uint64_t)u >= pthr)"),
+}
+
+
+@pytest.fixture(scope="module")
+def mutants(tmp_path_factory):
+    out = {}
+    d = tmp_path_factory.mktemp("mutants")
+    for name, (old, new) in MUTANTS.items():
+        assert SRC.count(old) == 1, name
+        src = d / f"{name}.c"
+        src.write_text(SRC.replace(old, new))
+        lib = str(d / f"lib{name}.so")
+        obuild.compile_oracle(str(src), lib)
+        out[name] = Oracle(lib)
+    return out
+
+
+def _fails(fn, *a, **k):
+    try:
+        fn(*a, **k)
+    except AssertionError:
+        return True
+    return False
+
+
+@pytest.mark.parametrize("name", ["no_checkerboard", "energy_sign", "wrong_neighbour"])
+def test_physics_pins_catch(mutants, name):
+    o = mutants[name]
+    assert _fails(pins.check_bruteforce, o, 4, 1.0, 0.0, 2.269185, sweeps=50_000)
+
+
+def test_observable_pins_catch_bond_sum(mutants):
+    o = mutants["bond_sum"]
+    assert _fails(pins.check_observables_definition, o)
+    assert _fails(pins.check_bm_histogram, o, 4, 1.0, 0.0, 2.269185, sweeps=100_000)
+
+
+def test_field_pin_catches_dropped_field(mutants):
+    o = mutants["field_dropped"]
+    assert _fails(pins.check_bruteforce, o, 4, 1.0, 0.1, 2.269185, sweeps=50_000)
+
+
+def test_kat_catches_philox_slip(mutants):
+    o = mutants["philox_key"]
+    got = [int(v) for v in o.philox([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
+                                    [0xa4093822, 0x299f31d0])]
+    assert got != [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_cross_oracle_catches_colour_order(mutants):
+    o = mutants["colour_order"]
+    a = o.init(16, 5, 0.5)
+    b = mini.initial_state(16, 5, 0.5)
+    Ba, _ = o.run(a, 1.0, 0.0, 2.269185, 5, 0, 10)
+    Bb, _ = mini.run(b, 1.0, 0.0, 2.269185, 5, 0, 10)
+    assert not np.array_equal(a, b)
+
+
+def test_init_pin_catches_compare(mutants):
+    o = mutants["init_compare"]
+    assert not np.all(o.init(16, 1, 1.0) == 1)
+
+
+def test_real_oracle_passes_the_same_checks(oracle1):
+    pins.check_observables_definition(oracle1)
+    pins.check_bm_histogram(oracle1, 4, 1.0, 0.0, 2.269185, sweeps=100_000)
+    pins.check_bruteforce(oracle1, 4, 1.0, 0.0, 2.269185, sweeps=50_000)
+    pins.check_bruteforce(oracle1, 4, 1.0, 0.1, 2.269185, sweeps=50_000)

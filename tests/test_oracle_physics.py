@@ -1,0 +1,215 @@
+"""Pins of the oracle's dynamics to results fixed by the mathematics.
+
+Section 2.2 of the paper defines the chain: energy -sum s_j s_k, consecutive
+black and white passes, Metropolis acceptance with the Boltzmann ratio. Its
+stationary law is the Boltzmann distribution, so exact enumeration (small
+lattices), Kaufman's finite-lattice solution and Onsager/Yang (large
+lattices) fix what the chain's averages must be. Exact special cases and
+integer invariants pin individual trajectories.
+"""
+import numpy as np
+import pytest
+
+from tests import physics, pins
+
+T_CFG = 2.269185  # the temperature the workloads call T_c
+
+
+@pytest.mark.parametrize("T", [1.5, T_CFG, 3.5])
+def test_bruteforce_4x4_zero_field(oracle1, T):
+    pins.check_bruteforce(oracle1, 4, 1.0, 0.0, T)
+
+
+def test_bruteforce_4x4_with_field(oracle1):
+    pins.check_bruteforce(oracle1, 4, 1.0, 0.1, T_CFG)
+
+
+def test_bruteforce_2x2_with_field(oracle1):
+    pins.check_bruteforce(oracle1, 2, 1.0, 0.3, 1.7)
+
+
+@pytest.mark.parametrize("L,T,h", [(4, T_CFG, 0.0), (4, 3.5, 0.1), (2, 2.6, 0.2)])
+def test_joint_bm_histogram(oracle1, L, T, h):
+    pins.check_bm_histogram(oracle1, L, 1.0, h, T)
+
+
+def test_half_sweep_transition_probabilities(oracle1):
+    pins.check_half_sweep_transitions(oracle1)
+
+
+def test_exact_half_sweep_detailed_balance(oracle1):
+    """Each one-colour pass satisfies detailed balance with respect to the
+    Boltzmann weights, pi(s) P_c(s->s') = pi(s') P_c(s'->s), up to the
+    threshold table's 2^-32 resolution; hence the full sweep P_0 P_1 leaves
+    pi stationary (it need not be reversible itself). Dense on 2x2, sampled
+    pairs on 4x4."""
+    J, h, T = 1.0, 0.2, 1.9
+    thr = oracle1.table(J, h, T)
+    _, B, M = physics.enumerate_states(2)
+    pi = physics.boltzmann_weights(B, M, J, h, T)
+    for c in (0, 1):
+        P, _ = pins.half_sweep_transition_matrix(thr, 2, c)
+        flow = pi[:, None] * P
+        assert np.abs(flow - flow.T).max() <= 2.0 ** -30
+        assert np.allclose(pi @ P, pi, atol=2.0 ** -30)
+    thr4 = oracle1.table(1.0, 0.0, T_CFG)
+    _, B4, M4 = physics.enumerate_states(4)
+    pi4 = physics.boltzmann_weights(B4, M4, 1.0, 0.0, T_CFG)
+    for c in (0, 1):
+        _sparse_check(thr4, 4, c, pi4)
+
+
+def _sparse_check(thr, L, c, pi):
+    """Detailed balance on the 4x4 lattice checked pairwise without a dense
+    matrix: for each state and each single flip of a colour-c site whose
+    reverse is a single flip too, compare the probability flows."""
+    states, _, _ = physics.enumerate_states(L)
+    colour = np.indices((L, L)).sum(axis=0) % 2
+    sites = np.argwhere(colour == c)
+    rng = np.random.default_rng(0)
+    weights = 1 << np.arange(L * L)
+    idx_of = lambda s: int((((s.reshape(-1) + 1) // 2) * weights).sum())
+
+    def prob(s, mask):
+        nb = np.roll(s, 1, 0) + np.roll(s, -1, 0) + np.roll(s, 1, 1) + np.roll(s, -1, 1)
+        pr = 1.0
+        for k, (i, j) in enumerate(sites):
+            p = int(thr[(1 if s[i, j] > 0 else 0) * 5 + (nb[i, j] + 4) // 2]) / 2.0 ** 32
+            pr *= p if (mask >> k) & 1 else 1.0 - p
+        return pr
+
+    for a in rng.choice(len(states), size=200, replace=False):
+        s = states[a]
+        for mask in rng.integers(0, 1 << len(sites), size=8):
+            t = s.copy()
+            for k, (i, j) in enumerate(sites):
+                if (mask >> k) & 1:
+                    t[i, j] = -t[i, j]
+            b = idx_of(t)
+            lhs = pi[a] * prob(s, mask)
+            rhs = pi[b] * prob(t, mask)
+            assert abs(lhs - rhs) <= 2.0 ** -30 * max(pi[a], pi[b]) * 16
+
+
+def test_kaufman_finite_lattice_at_tc(oracle1):
+    pins.check_kaufman(oracle1, 16, T_CFG)
+
+
+@pytest.mark.parametrize("T,p_up", [(1.5, 1.0), (3.5, 0.5)])
+def test_onsager_and_yang_far_from_tc(oracle, T, p_up):
+    pins.check_onsager(oracle, 64, T, p_up)
+
+
+def test_kaufman_formula_matches_enumeration():
+    import mpmath as mp
+    for L in (2, 4):
+        for T in (1.0, 2.269185, 3.5):
+            _, B, _ = physics.enumerate_states(L)
+            mp.mp.dps = 30
+            lnz = mp.log(mp.fsum(mp.exp(mp.mpf(int(b)) / T) for b in B))
+            assert abs(float(physics.kaufman_log_z(L, 1.0 / mp.mpf(T)) - lnz)) < 1e-12
+            assert abs(physics.kaufman_energy(L, T) - physics.exact_averages(L, 1.0, 0.0, T)["e"]) < 1e-10
+
+
+def test_infinite_temperature_flips_everything(oracle):
+    """T -> infinity: every threshold is 2^32, each pass flips its colour, so
+    after sweep t the lattice is (-1)^(t+1) s_0; B is unchanged, M alternates."""
+    L = 32
+    s0 = oracle.init(L, 4, 0.5)
+    b0, m0 = oracle.observables(s0)
+    s = s0.copy()
+    B, M = oracle.run(s, 1.0, 0.3, 1e300, 4, 0, 5)
+    assert np.array_equal(s, -s0)
+    assert list(B) == [b0] * 5
+    assert list(M) == [-m0, m0, -m0, m0, -m0]
+
+
+def test_zero_temperature_never_raises_energy(oracle):
+    """T -> 0: thresholds are 0 for every uphill move, so E never increases
+    (same-coloured flips share no bond, so a pass's energy change is the sum
+    of its accepted single-flip changes, all <= 0)."""
+    for h in (0.0, 0.05):
+        s = oracle.init(48, 8, 0.5)
+        B, M = oracle.run(s, 1.0, h, 1e-3, 8, 0, 200)
+        E = -B - h * M
+        assert np.all(np.diff(E) <= 1e-9)
+        assert E[-1] < E[0]
+
+
+def test_global_flip_symmetry(oracle):
+    """At h = 0 the rule is invariant under s -> -s with the same draws, so
+    the run from -s_0 is exactly the negation of the run from s_0; with a
+    field, the same holds when h is negated too."""
+    L = 40
+    for h in (0.0, 0.1):
+        s = oracle.init(L, 12, 0.5)
+        t = -s
+        B1, M1 = oracle.run(s, 1.0, h, T_CFG, 12, 0, 30)
+        B2, M2 = oracle.run(t, 1.0, -h, T_CFG, 12, 0, 30)
+        assert np.array_equal(t, -s)
+        assert np.array_equal(B1, B2) and np.array_equal(M1, -M2)
+
+
+def test_chunking_invariance(oracle):
+    L = 24
+    a = oracle.init(L, 2, 0.5)
+    b = a.copy()
+    Ba, Ma = oracle.run(a, 1.0, 0.05, 2.0, 2, 0, 50)
+    Bb1, Mb1 = oracle.run(b, 1.0, 0.05, 2.0, 2, 0, 20)
+    Bb2, Mb2 = oracle.run(b, 1.0, 0.05, 2.0, 2, 20, 30)
+    assert np.array_equal(a, b)
+    assert np.array_equal(Ba, np.concatenate([Bb1, Bb2]))
+    assert np.array_equal(Ma, np.concatenate([Mb1, Mb2]))
+
+
+@pytest.mark.parametrize("L", [2, 4, 6, 10, 64])
+def test_integer_invariants(oracle, L):
+    """Even L, periodic: M = N mod 2 = 0 mod 2; every periodic row and column
+    holds an even number of broken bonds, so B = 2N - 2*broken = 0 mod 4;
+    |B| <= 2N and |M| <= N."""
+    N = L * L
+    s = oracle.init(L, 31, 0.5)
+    B, M = oracle.run(s, 1.0, 0.07, 2.5, 31, 0, 200)
+    assert np.all(M % 2 == 0) and np.all(B % 4 == 0)
+    assert np.all(np.abs(B) <= 2 * N) and np.all(np.abs(M) <= N)
+    assert (B[-1], M[-1]) == oracle.observables(s)
+
+
+def test_observables_definition(oracle):
+    pins.check_observables_definition(oracle)
+
+
+def test_initial_state_probability(oracle):
+    """Section 2.2: each spin points up with probability p."""
+    L = 256
+    N = L * L
+    assert np.all(oracle.init(L, 1, 1.0) == 1)
+    assert np.all(oracle.init(L, 1, 0.0) == -1)
+    for p in (0.5, 0.3, 0.9):
+        up = int((oracle.init(L, 6, p) > 0).sum())
+        sd = np.sqrt(N * p * (1 - p))
+        assert abs(up - N * p) <= 4 * sd
+
+
+def test_clustering_low_t_randomness_high_t(oracle):
+    """Section 5 / Figure 2: spins cluster at low input temperature and look
+    random at high temperature."""
+    L = 64
+    s = oracle.init(L, 2, 1.0)
+    B, M = oracle.run(s, 1.0, 0.0, 1.5, 2, 0, 300)
+    assert abs(M[-1]) / (L * L) > 0.9 and B[-1] / (2 * L * L) > 0.9
+    s = oracle.init(L, 2, 0.5)
+    B, M = oracle.run(s, 1.0, 0.0, 4.0, 2, 0, 300)
+    assert abs(M[-100:]).mean() / (L * L) < 0.1 and B[-1] / (2 * L * L) < 0.5
+
+
+def test_invalid_arguments(oracle):
+    with pytest.raises(ValueError):
+        oracle.init(3, 1, 0.5)
+    with pytest.raises(ValueError):
+        oracle.init(8, 1, 1.5)
+    s = oracle.init(8, 1, 0.5)
+    with pytest.raises(ValueError):
+        oracle.run(s, 1.0, 0.0, 0.0, 1, 0, 1)
+    with pytest.raises(ValueError):
+        oracle.run(s, 1.0, 0.0, 1.0, 1, 2 ** 32 - 1, 2)
