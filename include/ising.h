@@ -1,0 +1,204 @@
+/*
+ * ising.h -- C ABI of the MI355X (gfx950) checkerboard Metropolis engine for
+ * the two-dimensional Ising model.
+ *
+ * The model and the update rule are those of Tomov, McGuigan, Bennett, Smith,
+ * Spiletic, "Benchmarking and Implementation of Probability-Based Simulations
+ * on Programmable Graphics Cards" (2003), Section 2.2:
+ *   - an L x L square lattice of spins s = +1 / -1, here with periodic
+ *     boundaries;
+ *   - energy E = -J sum_<jk> s_j s_k - h sum_j s_j (the paper's energy is the
+ *     case J = 1, h = 0), magnetisation M = #up - #down;
+ *   - a random initial state with spin-up probability p;
+ *   - checkerboard colouring: one sweep is the pass over colour 0
+ *     ((i + j) even, "black") followed by the pass over colour 1;
+ *   - Metropolis decision per site: flip if dE < 0, else draw R in [0, 1] and
+ *     flip if R <= exp(-dE / T) (Boltzmann constant 1, T in units of J).
+ *
+ * Choices the paper leaves open, fixed here so that every result is
+ * reproducible bit for bit:
+ *   - Draws. Philox4x32-10 (Salmon et al., SC 2011). The sites of colour c are
+ *     numbered ord = (i*L + j) / 2; the four sites ord = 4q .. 4q+3 share the
+ *     call with counter (q, t, c, d) and key (seed & 0xffffffff, seed >> 32)
+ *     and take output word ord % 4. t is the absolute sweep index, d = 0 for
+ *     Metropolis decisions and d = 1 for the initial state (drawn at t = 0).
+ *   - Acceptance. R = (u + 1) / 2^32 for the 32-bit draw u, so the flip
+ *     happens iff u < thr(s, n), thr = floor(exp(-dE/T) * 2^32) evaluated in
+ *     IEEE double as exp(-(2.0 * s * (J * n + h)) / T) with n the sum of the
+ *     four neighbours, and thr = 2^32 when dE <= 0.
+ *   - Initial state: up iff u < floor(p_up * 2^32).
+ *   - Observables after sweep t: bond sum B_t = sum_{i,j} s(i,j) (s(i,j+1) +
+ *     s(i+1,j)) (every edge once) and M_t = sum s, both exact int64; the
+ *     energy is E = -J B - h M.
+ *   - Canonical lattice bytes: row-major int8, +1 -> 0x01, -1 -> 0xFF.
+ *     Lattice hash: FNV-1a 64 over those L*L bytes.
+ *
+ * Device memory is HIP device memory of the current device; streams are
+ * hipStream_t passed as void* (NULL = the library creates its own stream).
+ * All sweep calls are asynchronous on the context's stream; calls that return
+ * host data synchronise that stream. A context must not be used by two host
+ * threads at once. Every entry point returns ISING_OK or a negative error
+ * code and never throws. On a HIP error the context is poisoned: later calls
+ * return ISING_ESTATE and only ising_destroy is valid.
+ */
+#ifndef ISING_MI355X_H
+#define ISING_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISING_OK 0
+#define ISING_EINVAL (-1)      /* bad argument (odd or too large L, T <= 0, NaN, NULL ...) */
+#define ISING_ENOMEM (-2)      /* device or host allocation failed */
+#define ISING_EDEVICE (-3)     /* a HIP call failed; the context is now poisoned */
+#define ISING_ERANGE (-4)      /* sweep index would pass 2^32 - 1, or a buffer is too small */
+#define ISING_EUNSUPPORTED (-5) /* valid request this build cannot serve */
+#define ISING_ESTATE (-6)      /* context poisoned by an earlier device error */
+
+#define ISING_MAX_L 65536u     /* counter word 0 holds site/8: L*L/8 must fit 32 bits */
+
+/* Plan selection (ising_params.flags, low byte). AUTO picks per lattice side:
+ * the fused one-pass sweep for large sides, the workgroup-resident kernel
+ * for small ones, the two-pass in-place sweep otherwise. The others force a
+ * path (ISING_EUNSUPPORTED if the side does not fit that path). */
+#define ISING_PLAN_AUTO 0u
+#define ISING_PLAN_TWO_PASS 1u  /* one launch per colour, in place */
+#define ISING_PLAN_FUSED 2u     /* one launch per sweep, ping-pong buffers */
+#define ISING_PLAN_RESIDENT 3u  /* one workgroup runs all sweeps of the call */
+#define ISING_PLAN_GENERIC 4u   /* per-site draws; the only path for L % 8 != 0 */
+
+/* Model and run parameters (Section 2.2: L x L lattice, coupling J, field h,
+ * temperature T, spin-up probability p_up of the initial state). */
+typedef struct ising_params {
+    uint32_t L;      /* side, even, 2 <= L <= ISING_MAX_L */
+    uint32_t flags;  /* ISING_PLAN_* */
+    double J;        /* coupling, finite */
+    double h;        /* field, finite */
+    double T;        /* temperature, finite and > 0 */
+    uint64_t seed;   /* Philox key */
+    double p_up;     /* in [0, 1] */
+} ising_params;
+
+/* Current state summary (Eq. (1) of Section 2.1 is estimated by averaging
+ * these over sweeps; see ising_series_averages). */
+typedef struct ising_obs {
+    uint64_t sweeps_done;  /* absolute sweep index t of the next sweep */
+    int64_t bond_sum;      /* B of the current lattice */
+    int64_t mag_sum;       /* M of the current lattice */
+    double energy;         /* -J B - h M */
+    double e_per_site;     /* energy / L^2 */
+    double m_per_site;     /* M / L^2 */
+    uint64_t lattice_hash; /* FNV-1a 64 of the canonical bytes (if requested) */
+    uint64_t series_len;   /* per-sweep (B_t, M_t) pairs pending on the device */
+} ising_obs;
+
+/* Averages over a window of the per-sweep series, summed in increasing t in
+ * IEEE double (Eq. (1) estimated as a plain time average). */
+typedef struct ising_averages {
+    uint64_t n;       /* sweeps in the window */
+    double e;         /* <E / N> */
+    double e2;        /* <(E / N)^2> */
+    double m;         /* <M / N> */
+    double abs_m;     /* <|M| / N> */
+    double m2;        /* <(M / N)^2> */
+} ising_averages;
+
+#define ISING_OBS_HASH 1u    /* compute lattice_hash (copies the lattice to the host) */
+#define ISING_OBS_SERIES 2u  /* copy out and clear the pending per-sweep series */
+
+typedef struct ising_ctx ising_ctx; /* opaque, library-owned */
+
+/* Bytes of device memory the lattice state of a context for side L uses
+ * under the given plan flags (the per-sweep series buffer is separate and
+ * library-owned). Returns 0 for an invalid L or a plan that cannot serve it. */
+size_t ising_state_bytes(uint32_t L, uint32_t flags);
+
+/* Create a context: validate `params`, allocate its device buffers, build the
+ * acceptance table on the host and draw the initial state (Section 2.2) on
+ * `stream` (NULL: the library creates and owns a stream). The context starts
+ * at sweep t = 0. *out is set to the context, or to NULL on failure.
+ * Errors: EINVAL (invalid params or out == NULL), EUNSUPPORTED (forced plan
+ * cannot serve L), ENOMEM, EDEVICE. */
+int ising_create(const ising_params* params, void* stream, ising_ctx** out);
+
+/* As ising_create, but the lattice state lives in caller-owned device memory
+ * `dev_buf` of `bytes` >= ising_state_bytes(L, flags) bytes (for example a
+ * PyTorch tensor). The buffer must stay allocated until ising_destroy; its
+ * layout is internal (read the lattice with ising_copy_spins). */
+int ising_create_in(const ising_params* params, void* dev_buf, size_t bytes, void* stream,
+                    ising_ctx** out);
+
+/* Enqueue n full sweeps (colour 0 then colour 1, Section 2.2) on the
+ * context's stream, for sweep indices t .. t+n-1, and record (B_t, M_t)
+ * after each. Asynchronous. n = 0 is a no-op. Errors: EINVAL (NULL ctx),
+ * ERANGE (t + n > 2^32), ESTATE, ENOMEM (series buffer growth), EDEVICE. */
+int ising_sweep(ising_ctx* ctx, uint64_t n);
+
+/* Synchronise the context's stream and report the current state in *out
+ * (may be NULL). With ISING_OBS_HASH the lattice is copied to the host and
+ * hashed. With ISING_OBS_SERIES the pending per-sweep series (oldest first)
+ * is copied into bond_series / mag_series (host arrays of `capacity`
+ * entries; either may be NULL to skip it) and then cleared; ERANGE if
+ * capacity is smaller than the pending length (nothing is cleared then). */
+int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int64_t* mag_series,
+                      uint64_t capacity, uint32_t want);
+
+/* Copy the current lattice to host memory `host` of n >= L*L bytes in the
+ * canonical layout (row-major int8, +1 / -1). Synchronises. */
+int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n);
+
+/* Replace the lattice by host canonical bytes (n >= L*L, every byte +1 or
+ * -1, else EINVAL) and set the sweep index to t (checkpoint restore; the
+ * counter-based draws make a restored run continue exactly). Clears the
+ * pending series. Synchronises. */
+int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
+
+/* Run n_sweeps[k] sweeps on ctxs[k], k < count, as one persistent launch
+ * (plus a small reset launch) on `stream` (NULL: the first context's
+ * stream): each workgroup takes whole lattices, largest work first, and
+ * runs all of their sweeps. Lattices may differ in L, J, h, T and seed;
+ * each must satisfy L % 8 == 0 and have no pending device error. Contexts
+ * are validated before anything is launched (all-or-nothing). The results
+ * are bit-identical to calling ising_sweep on each context alone.
+ * Asynchronous; the contexts' own streams are ordered after it. */
+int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream);
+
+/* Plain time averages of a series window of n sweeps for an L x L lattice
+ * with coupling J and field h (host only, no device work). */
+int ising_series_averages(const int64_t* bond_series, const int64_t* mag_series, uint64_t n,
+                          uint32_t L, double J, double h, ising_averages* out);
+
+/* Plan the context runs with: ISING_PLAN_* and, for tunable plans, the
+ * chunk width in 32-bit words and the rows per thread. */
+int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
+                    uint32_t* rows_per_thread);
+
+/* Force the plan of a context (ISING_PLAN_*; for ISING_PLAN_FUSED also the
+ * chunk width cw in {1, 2, 4} words per lane and the tile height rows in
+ * {8, 16, 32, 64}; 0 picks a default). Switching to the fused plan may
+ * allocate a second lattice buffer. Results do not depend on the plan.
+ * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */
+int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
+
+/* Autotuner: time `trial_sweeps` sweeps of every plan and fused tile shape
+ * that can serve the context's L on a scratch copy of its lattice (the
+ * context's own state is untouched), switch the context to the fastest and
+ * remember it for later AUTO contexts of the same L in this process.
+ * Synchronises. The chosen plan is readable with ising_plan_info. */
+int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps);
+
+/* Release the context and its library-owned device memory. NULL is a no-op.
+ * Synchronises the context's stream first. */
+int ising_destroy(ising_ctx* ctx);
+
+/* Static description of an error code. */
+const char* ising_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,256 @@
+"""ctypes binding of the C ABI in include/ising.h (argument marshalling only).
+
+Every function keeps the C name and returns what the C call returns in its
+out-parameters; a negative status raises IsingError. Device memory and
+streams may come from PyTorch: pass ``tensor.data_ptr()`` and
+``torch.cuda.Stream().cuda_stream`` as integers.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libising_mi355x.so")
+
+ISING_OK = 0
+ISING_EINVAL = -1
+ISING_ENOMEM = -2
+ISING_EDEVICE = -3
+ISING_ERANGE = -4
+ISING_EUNSUPPORTED = -5
+ISING_ESTATE = -6
+
+ISING_MAX_L = 65536
+
+ISING_PLAN_AUTO = 0
+ISING_PLAN_TWO_PASS = 1
+ISING_PLAN_FUSED = 2
+ISING_PLAN_RESIDENT = 3
+ISING_PLAN_GENERIC = 4
+
+ISING_OBS_HASH = 1
+ISING_OBS_SERIES = 2
+
+
+class ising_params(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("flags", C.c_uint32), ("J", C.c_double), ("h", C.c_double),
+                ("T", C.c_double), ("seed", C.c_uint64), ("p_up", C.c_double)]
+
+
+class ising_obs(C.Structure):
+    _fields_ = [("sweeps_done", C.c_uint64), ("bond_sum", C.c_int64), ("mag_sum", C.c_int64),
+                ("energy", C.c_double), ("e_per_site", C.c_double), ("m_per_site", C.c_double),
+                ("lattice_hash", C.c_uint64), ("series_len", C.c_uint64)]
+
+
+class ising_averages(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("e", C.c_double), ("e2", C.c_double), ("m", C.c_double),
+                ("abs_m", C.c_double), ("m2", C.c_double)]
+
+
+class IsingError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        msg = lib().ising_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+# Every entry point declared in include/ising.h, with its ctypes signature.
+SIGNATURES = {
+    "ising_state_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
+    "ising_create": (C.c_int, [C.POINTER(ising_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ising_create_in": (C.c_int, [C.POINTER(ising_params), C.c_void_p, C.c_size_t, C.c_void_p,
+                                  C.POINTER(C.c_void_p)]),
+    "ising_sweep": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ising_observables": (C.c_int, [C.c_void_p, C.POINTER(ising_obs), C.c_void_p, C.c_void_p, C.c_uint64,
+                                    C.c_uint32]),
+    "ising_copy_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "ising_load_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64]),
+    "ising_sweep_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p]),
+    "ising_series_averages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_double,
+                                        C.c_double, C.POINTER(ising_averages)]),
+    "ising_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                  C.POINTER(C.c_uint32)]),
+    "ising_plan_set": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
+    "ising_tune": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "ising_destroy": (C.c_int, [C.c_void_p]),
+    "ising_strerror": (C.c_char_p, [C.c_int]),
+}
+
+_lib = None
+
+
+def _share_torch_hip_runtime():
+    """PyTorch ships its own HIP runtime (same soname as ROCm's). Loading it
+    first makes the library bind to that one, so torch tensors, streams and
+    this library share one runtime in the process."""
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+
+
+def lib(path=None):
+    """Load the HIP library (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError(f"{p} is missing: build it with paper_cs_0312006_amd/build.py")
+    _share_torch_hip_runtime()
+    handle = C.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(handle, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = handle
+    return handle
+
+
+def _check(rc, what):
+    if rc != ISING_OK:
+        raise IsingError(rc, what)
+
+
+def _params(L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO):
+    return ising_params(int(L), int(flags), float(J), float(h), float(T), int(seed) & (2 ** 64 - 1),
+                        float(p_up))
+
+
+def ising_state_bytes(L, flags=ISING_PLAN_AUTO):
+    return int(lib().ising_state_bytes(int(L), int(flags)))
+
+
+def ising_create(L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO, stream=None):
+    """Returns an opaque context handle (int)."""
+    p = _params(L, J, h, T, seed, p_up, flags)
+    out = C.c_void_p()
+    _check(lib().ising_create(C.byref(p), stream, C.byref(out)), "ising_create")
+    return out.value
+
+
+def ising_create_in(dev_ptr, nbytes, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO,
+                    stream=None):
+    p = _params(L, J, h, T, seed, p_up, flags)
+    out = C.c_void_p()
+    _check(lib().ising_create_in(C.byref(p), C.c_void_p(dev_ptr), int(nbytes), stream, C.byref(out)),
+           "ising_create_in")
+    return out.value
+
+
+def ising_sweep(ctx, n):
+    _check(lib().ising_sweep(ctx, int(n)), "ising_sweep")
+
+
+def ising_observables(ctx, want=0, capacity=None):
+    """Returns (ising_obs, bond_series or None, mag_series or None)."""
+    obs = ising_obs()
+    bs = ms = None
+    pb = pm = None
+    cap = 0
+    if want & ISING_OBS_SERIES:
+        if capacity is None:
+            rc = lib().ising_observables(ctx, C.byref(obs), None, None, 0, 0)
+            _check(rc, "ising_observables")
+            capacity = obs.series_len
+        cap = int(capacity)
+        bs = np.zeros(cap, dtype=np.int64)
+        ms = np.zeros(cap, dtype=np.int64)
+        pb, pm = bs.ctypes.data, ms.ctypes.data
+    _check(lib().ising_observables(ctx, C.byref(obs), pb, pm, cap, int(want)), "ising_observables")
+    if bs is not None:
+        n = obs.series_len
+        bs, ms = bs[:n], ms[:n]
+    return obs, bs, ms
+
+
+def ising_copy_spins(ctx, L):
+    out = np.empty((L, L), dtype=np.int8)
+    _check(lib().ising_copy_spins(ctx, out.ctypes.data, out.size), "ising_copy_spins")
+    return out
+
+
+def ising_load_spins(ctx, spins, t):
+    a = np.ascontiguousarray(spins, dtype=np.int8)
+    _check(lib().ising_load_spins(ctx, a.ctypes.data, a.size, int(t)), "ising_load_spins")
+
+
+def ising_sweep_batch(ctxs, n_sweeps, stream=None):
+    k = len(ctxs)
+    arr = (C.c_void_p * k)(*ctxs)
+    ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
+    _check(lib().ising_sweep_batch(arr, ns, k, stream), "ising_sweep_batch")
+
+
+def ising_series_averages(bond, mag, L, J=1.0, h=0.0):
+    b = np.ascontiguousarray(bond, dtype=np.int64)
+    m = np.ascontiguousarray(mag, dtype=np.int64)
+    out = ising_averages()
+    _check(lib().ising_series_averages(b.ctypes.data, m.ctypes.data, len(b), int(L), float(J), float(h),
+                                       C.byref(out)), "ising_series_averages")
+    return out
+
+
+def ising_plan_info(ctx):
+    p, cw, r = C.c_uint32(), C.c_uint32(), C.c_uint32()
+    _check(lib().ising_plan_info(ctx, C.byref(p), C.byref(cw), C.byref(r)), "ising_plan_info")
+    return p.value, cw.value, r.value
+
+
+def ising_plan_set(ctx, plan, cw=0, rows=0):
+    _check(lib().ising_plan_set(ctx, int(plan), int(cw), int(rows)), "ising_plan_set")
+
+
+def ising_tune(ctx, trial_sweeps=4):
+    _check(lib().ising_tune(ctx, int(trial_sweeps)), "ising_tune")
+
+
+def ising_destroy(ctx):
+    _check(lib().ising_destroy(ctx), "ising_destroy")
+
+
+def ising_strerror(code):
+    return lib().ising_strerror(int(code)).decode()
+
+
+class Lattice:
+    """Convenience owner of one context (destroyed on close / garbage)."""
+
+    def __init__(self, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO, stream=None):
+        self.L, self.J, self.h = int(L), float(J), float(h)
+        self.ctx = ising_create(L, J, h, T, seed, p_up, flags, stream)
+
+    def sweep(self, n):
+        ising_sweep(self.ctx, n)
+
+    def observables(self, want=ISING_OBS_SERIES):
+        return ising_observables(self.ctx, want)
+
+    def spins(self):
+        return ising_copy_spins(self.ctx, self.L)
+
+    def load(self, spins, t):
+        ising_load_spins(self.ctx, spins, t)
+
+    def plan(self):
+        return ising_plan_info(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            ising_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

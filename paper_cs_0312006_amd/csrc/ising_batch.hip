@@ -1,0 +1,148 @@
+// Workgroup-resident sweeps for many independent lattices in one launch.
+//
+// Each workgroup takes the next lattice from a device work queue (the host
+// orders the queue by work, largest first) and runs all of that lattice's
+// sweeps itself: colour 0 of sweep t, a workgroup barrier, colour 1, a
+// barrier, then the sweep's (B, M) (Section 2.2's consecutive black and
+// white passes). Lattices stay in their own colour planes and are updated
+// in place; small ones live in the L1/L2 of the workgroup's CU for the whole
+// run. The grid is sized to the resident capacity of the chip, so the kernel
+// is persistent: no workgroup waits on another.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t kBatchThreads = 512;
+
+template <int CW, bool OBS, bool EXACT>
+__device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem& it, uint32_t c, uint32_t t,
+                                            uint32_t& sad, uint32_t& ups) {
+    uint32_t* own = c ? it.p1 : it.p0;
+    const uint32_t* oth = c ? it.p0 : it.p1;
+    const uint32_t L = it.L, Hw = it.Hw;
+    const uint32_t per_row = Hw / CW;
+    const uint32_t total = L * per_row;
+    for (uint32_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const uint32_t i = idx / per_row;
+        const uint32_t wc = (idx - i * per_row) * CW;
+        const uint32_t iu = i == 0 ? L - 1 : i - 1;
+        const uint32_t id = i + 1 == L ? 0 : i + 1;
+        const uint32_t p = (i + c) & 1u;
+        const size_t row = (size_t)i * Hw;
+        uint32_t W[CW], U[CW], D[CW], O[CW];
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+            W[w] = own[row + wc + w];
+            U[w] = oth[(size_t)iu * Hw + wc + w];
+            D[w] = oth[(size_t)id * Hw + wc + w];
+            O[w] = oth[row + wc + w];
+        }
+        const uint32_t ew = p ? (wc + CW == Hw ? 0u : wc + CW) : (wc == 0 ? Hw - 1 : wc - 1);
+        const uint32_t E = oth[row + ew];
+#pragma unroll
+        for (int w = 0; w < CW; ++w) {
+            const uint32_t nxt = (w + 1 < CW) ? O[(w + 1 < CW) ? w + 1 : 0] : E;
+            const uint32_t prv = (w > 0) ? O[(w > 0) ? w - 1 : 0] : E;
+            const uint32_t S = shifted(O[w], nxt, prv, p);
+            const uint32_t n = U[w] + D[w] + O[w] + S;
+            const uint4 r = philox((uint32_t)(row + wc + w), t, c, 0u, it.k0, it.k1);
+            const uint32_t Wn = W[w] ^ flip_mask<EXACT>(lt, W[w], n, r);
+            own[row + wc + w] = Wn;
+            if (OBS) {
+                sad = sad_misaligned(Wn, n, sad);
+                ups += __builtin_popcount(Wn) + __builtin_popcount(O[w]);
+            }
+        }
+    }
+}
+
+template <int CW, bool EXACT>
+__device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem& it, int64_t (*red)[16]) {
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t nwaves = blockDim.x >> 6;
+    for (uint32_t s = 0; s < it.n; ++s) {
+        const uint32_t t = it.t0 + s;
+        uint32_t sad = 0, ups = 0;
+        colour_pass<CW, false, EXACT>(lt, it, 0u, t, sad, ups);
+        __syncthreads();
+        colour_pass<CW, true, EXACT>(lt, it, 1u, t, sad, ups);
+        // words of colour 1 this thread updated
+        const uint32_t total = it.L * (it.Hw / CW);
+        const uint32_t mine = threadIdx.x < total ? (total - 1 - threadIdx.x) / blockDim.x + 1 : 0u;
+        const int64_t nw = (int64_t)mine * CW;
+        int64_t b = 16 * nw - 2 * (int64_t)sad;
+        int64_t m = 2 * (int64_t)ups - 8 * nw;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            b += __shfl_xor(b, off, 64);
+            m += __shfl_xor(m, off, 64);
+        }
+        if (lane == 0) {
+            red[0][wv] = b;
+            red[1][wv] = m;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t sb = 0, sm = 0;
+            for (uint32_t w = 0; w < nwaves; ++w) {
+                sb += red[0][w];
+                sm += red[1][w];
+            }
+            it.series[2 * s] = sb;
+            it.series[2 * s + 1] = sm;
+        }
+        // the next colour-0 pass reads this sweep's colour 1, and red[] is
+        // not written again before two more barriers
+    }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __restrict__ items,
+                                                         const uint32_t* __restrict__ order, BatchHeader* hdr) {
+    __shared__ LdsTable lt;
+    __shared__ uint32_t s_slot;
+    __shared__ int64_t red[2][16];
+    const uint32_t count = hdr->count;
+    for (;;) {
+        if (threadIdx.x == 0) s_slot = atomicAdd(&hdr->head, 1u);
+        __syncthreads();
+        const uint32_t slot = s_slot;
+        if (slot >= count) break;
+        const BatchItem& it = items[order[slot]];
+        load_table(lt, it.table);
+        __syncthreads();
+        const uint32_t key = it.cw * 2u + it.exact;
+        switch (key) {
+            case 8: run_lattice<4, false>(lt, it, red); break;
+            case 9: run_lattice<4, true>(lt, it, red); break;
+            case 4: run_lattice<2, false>(lt, it, red); break;
+            case 5: run_lattice<2, true>(lt, it, red); break;
+            case 2: run_lattice<1, false>(lt, it, red); break;
+            default: run_lattice<1, true>(lt, it, red); break;
+        }
+        // everyone has read s_slot and the table before they are replaced
+        __syncthreads();
+    }
+}
+
+uint32_t batch_block_threads() { return kBatchThreads; }
+
+hipError_t batch_occupancy(int* blocks_per_cu) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, (int)kBatchThreads, 0);
+}
+
+hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,
+                        hipStream_t s) {
+    if (grid == 0) return hipSuccess;
+    k_batch<<<grid, kBatchThreads, 0, s>>>(items, order, hdr);
+    return hipGetLastError();
+}
+
+}  // namespace ising

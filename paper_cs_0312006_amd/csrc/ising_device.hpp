@@ -1,0 +1,148 @@
+// Device building blocks of the gfx950 checkerboard Metropolis engine.
+//
+// Lattice storage ("colour planes"): the sites of colour c = (i + j) & 1 of
+// row i are stored contiguously in plane c, row i, at byte m = j >> 1, so a
+// row of a plane holds H = L/2 bytes and plane c's byte (i, m) is the site
+// j = 2m + ((i + c) & 1). This is the two-lattice layout Section 5 of the
+// paper proposes to remove the checkerboard branch. Each byte is 1 for an up
+// spin and 0 for a down spin, so four sites pack into a 32-bit word and
+// neighbour counts are byte-wise sums (SWAR), never exceeding 4.
+//
+// Neighbours of plane-c byte (i, m), with p = (i + c) & 1, all in plane 1-c:
+// (i-1, m), (i+1, m), (i, m) and (i, m-1) if p == 0 or (i, m+1) if p == 1,
+// indices taken modulo L rows and H bytes.
+//
+// Draw keying (fixed by the public header): site ordinal ord = i*H + m within
+// its colour, Philox counter (ord >> 2, t, c, d). When H % 4 == 0 a 32-bit
+// word of a plane row is exactly one Philox call: q = i*(H/4) + word, and
+// output word b belongs to byte b.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ising {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+// a ^ b ^ c in one gfx950 VALU op (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// Philox4x32-10 (Salmon et al., SC 2011) of counter (q, c1, c2, c3) and key
+// (k0, k1). Only q varies across lanes in this engine; c1..c3 and the key are
+// wave-uniform, so the uniform halves of the first rounds stay on the scalar
+// unit and the vector cost is about 37 ops per call: each later round is two
+// 32x32->64 multiplies (v_mad_u64_u32) and two three-way XORs.
+__device__ __forceinline__ uint4 philox(uint32_t q, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+    uint32_t x0 = q, x1 = c1, x2 = c2, x3 = c3;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * x0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * x2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), hi1 = (uint32_t)(p1 >> 32);
+        uint32_t y0, y2;
+        if (r < 2) {  // at least one operand of each XOR is uniform
+            y0 = hi1 ^ x1 ^ k0;
+            y2 = hi0 ^ x3 ^ k1;
+        } else if (r == 2) {  // x3 is still uniform here
+            y0 = xor3(hi1, x1, k0);
+            y2 = hi0 ^ x3 ^ k1;
+        } else {
+            y0 = xor3(hi1, x1, k0);
+            y2 = xor3(hi0, x3, k1);
+        }
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = y0;
+        x2 = y2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return make_uint4(x0, x1, x2, x3);
+}
+
+// Acceptance tables, indexed by code = 8*s + n (s = spin bit, n = number of
+// up neighbours, 0..4). thr_m1[code] = thr - 1 (accept iff u <= thr_m1),
+// valid when no threshold is 0; thr_lo/thr_hi hold the full thr in [0, 2^32]
+// for the exact path (accept iff u < thr) used when some threshold is 0.
+struct AcceptTable {
+    uint32_t thr_m1[16];
+    uint32_t thr_lo[16];
+    uint32_t thr_hi[16];
+};
+
+// LDS copy of the table. t32 is read at byte offset 4*code, t64 at 8*code.
+struct LdsTable {
+    uint32_t t32[16];
+    uint2 t64[16];
+};
+
+__device__ __forceinline__ void load_table(LdsTable& lt, const AcceptTable& at) {
+    const uint32_t tid = threadIdx.x;
+    if (tid < 16) {
+        lt.t32[tid] = at.thr_m1[tid];
+        lt.t64[tid] = make_uint2(at.thr_lo[tid], at.thr_hi[tid]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_at(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Flip mask of one word of four sites: byte b is 1 when site b's move is
+// accepted. W holds the four spin bits, n the four up-neighbour counts and
+// r the four draws of the word's Philox call.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t flip_mask(const LdsTable& lt, uint32_t W, uint32_t n, uint4 r) {
+    if (!EXACT) {
+        const uint32_t code4 = (W << 5) | (n << 2);  // per byte: 4 * (8 s + n)
+        const uint32_t a0 = lds_at(lt.t32, code4 & 0xffu);
+        const uint32_t a1 = lds_at(lt.t32, (code4 >> 8) & 0xffu);
+        const uint32_t a2 = lds_at(lt.t32, (code4 >> 16) & 0xffu);
+        const uint32_t a3 = lds_at(lt.t32, code4 >> 24);
+        const uint32_t f0 = r.x <= a0 ? 0x00000001u : 0u;
+        const uint32_t f1 = r.y <= a1 ? 0x00000100u : 0u;
+        const uint32_t f2 = r.z <= a2 ? 0x00010000u : 0u;
+        const uint32_t f3 = r.w <= a3 ? 0x01000000u : 0u;
+        return (f0 | f1) | (f2 | f3);
+    } else {
+        const uint32_t code8 = (W << 6) | (n << 3);  // per byte: 8 * (8 s + n)
+        const uint2 a0 = lds_at(lt.t64, code8 & 0xffu);
+        const uint2 a1 = lds_at(lt.t64, (code8 >> 8) & 0xffu);
+        const uint2 a2 = lds_at(lt.t64, (code8 >> 16) & 0xffu);
+        const uint2 a3 = lds_at(lt.t64, code8 >> 24);
+        auto lt64 = [](uint32_t u, uint2 a) {
+            return (uint64_t)u < (((uint64_t)a.y << 32) | a.x);
+        };
+        const uint32_t f0 = lt64(r.x, a0) ? 0x00000001u : 0u;
+        const uint32_t f1 = lt64(r.y, a1) ? 0x00000100u : 0u;
+        const uint32_t f2 = lt64(r.z, a2) ? 0x00010000u : 0u;
+        const uint32_t f3 = lt64(r.w, a3) ? 0x01000000u : 0u;
+        return (f0 | f1) | (f2 | f3);
+    }
+}
+
+// Same-row neighbour word: bytes m+1..m+4 (p == 1) or m-1..m+2 (p == 0) of
+// the other plane, from the word O at m..m+3 and the word after / before it.
+__device__ __forceinline__ uint32_t shifted(uint32_t O, uint32_t O_next, uint32_t O_prev, uint32_t p) {
+    return p ? __builtin_amdgcn_alignbyte(O_next, O, 1) : __builtin_amdgcn_alignbyte(O, O_prev, 3);
+}
+
+// Observable partial sums of one updated colour-1 word (new spins Wn, up
+// counts n of its colour-0 neighbours). Each lattice edge joins colour 0 to
+// colour 1, so the bond sum is sum over colour-1 sites of s * (sum of
+// neighbours) = sum over those sites of (2 a - 4), a = neighbours aligned
+// with the site = 4 - |4 s - n|. Per word: B = 16 - 2 * sum_b |4 s_b - n_b|,
+// one v_sad_u8.
+__device__ __forceinline__ uint32_t sad_misaligned(uint32_t Wn, uint32_t n, uint32_t acc) {
+    return __builtin_amdgcn_sad_u8(Wn << 2, n, acc);
+}
+
+}  // namespace ising

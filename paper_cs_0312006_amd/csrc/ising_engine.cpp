@@ -1,0 +1,214 @@
+// Batch engine: runs many contexts' sweeps as one persistent, workgroup-
+// resident launch (ising_batch.hip), replayed from a captured hipGraph.
+//
+// Per device the engine owns a device array of lattice descriptors, the
+// queue order and a header, plus pinned host copies used to stage them. A
+// call stages the descriptors (longest work first), copies them with one
+// async copy each, and replays the graph, whose single kernel node reads
+// them; the graph is captured once per buffer generation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "ising.h"
+#include "ising_launch.hpp"
+#include "ising_runtime.hpp"
+
+using namespace ising;
+
+namespace {
+
+struct Engine {
+    std::mutex mu;
+    bool ready = false;
+    size_t cap = 0;
+    BatchItem* d_items = nullptr;
+    uint32_t* d_order = nullptr;
+    BatchHeader* d_hdr = nullptr;
+    BatchItem* h_items = nullptr;
+    uint32_t* h_order = nullptr;
+    BatchHeader* h_hdr = nullptr;
+    hipEvent_t staged = nullptr;  // completion of the last staging copies
+    hipEvent_t order_ev = nullptr;
+    hipEvent_t done = nullptr;    // completion of the last launch (any stream)
+    bool staged_pending = false;
+    bool launched = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t grid = 0;
+};
+
+constexpr int kMaxDevices = 64;
+Engine g_engines[kMaxDevices];
+
+void release_buffers(Engine& e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    e.exec = nullptr;
+    e.graph = nullptr;
+    if (e.d_items) (void)hipFree(e.d_items);
+    if (e.d_order) (void)hipFree(e.d_order);
+    if (e.d_hdr) (void)hipFree(e.d_hdr);
+    if (e.h_items) (void)hipHostFree(e.h_items);
+    if (e.h_order) (void)hipHostFree(e.h_order);
+    if (e.h_hdr) (void)hipHostFree(e.h_hdr);
+    e.d_items = nullptr;
+    e.d_order = nullptr;
+    e.d_hdr = nullptr;
+    e.h_items = nullptr;
+    e.h_order = nullptr;
+    e.h_hdr = nullptr;
+    e.cap = 0;
+}
+
+hipError_t ensure_capacity(Engine& e, size_t count) {
+    if (count <= e.cap) return hipSuccess;
+    if (e.staged_pending) {
+        hipError_t r = hipEventSynchronize(e.staged);
+        if (r != hipSuccess) return r;
+        e.staged_pending = false;
+    }
+    // the previous graph may still be running on some stream: drain
+    hipError_t r = hipDeviceSynchronize();
+    if (r != hipSuccess) return r;
+    release_buffers(e);
+    size_t cap = 256;
+    while (cap < count) cap *= 2;
+    if ((r = hipMalloc(&e.d_items, cap * sizeof(BatchItem))) != hipSuccess) return r;
+    if ((r = hipMalloc(&e.d_order, cap * sizeof(uint32_t))) != hipSuccess) return r;
+    if ((r = hipMalloc(&e.d_hdr, sizeof(BatchHeader))) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_items, cap * sizeof(BatchItem), hipHostMallocDefault)) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_order, cap * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess) return r;
+    e.cap = cap;
+    return hipSuccess;
+}
+
+hipError_t init_engine(Engine& e) {
+    if (e.ready) return hipSuccess;
+    hipError_t r = hipEventCreateWithFlags(&e.staged, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    r = hipEventCreateWithFlags(&e.order_ev, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    r = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if ((r = hipGetDevice(&dev)) != hipSuccess) return r;
+    if ((r = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return r;
+    int per_cu = 0;
+    if ((r = batch_occupancy(&per_cu)) != hipSuccess) return r;
+    if (per_cu < 1) per_cu = 1;
+    e.grid = (uint32_t)prop.multiProcessorCount * (uint32_t)per_cu;
+    e.ready = true;
+    return hipSuccess;
+}
+
+// Capture the single persistent launch into a graph (once per buffer set).
+hipError_t ensure_graph(Engine& e, hipStream_t s) {
+    if (e.exec) return hipSuccess;
+    hipStream_t cap = nullptr;
+    hipError_t r = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (r != hipSuccess) return r;
+    r = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (r == hipSuccess) {
+        hipError_t lr = launch_batch(e.d_items, e.d_order, e.d_hdr, e.grid, cap);
+        r = hipStreamEndCapture(cap, &e.graph);
+        if (lr != hipSuccess) r = lr;
+    }
+    if (r == hipSuccess) r = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    (void)s;
+    return r;
+}
+
+}  // namespace
+
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s) {
+    int dev = ctxs[0]->device;
+    if (dev < 0 || dev >= kMaxDevices) return ISING_EINVAL;
+    // series room first (may synchronise the contexts' streams)
+    for (size_t k = 0; k < count; ++k) {
+        if (n[k] == 0) continue;
+        int rc = ctx_reserve_series(ctxs[k], n[k]);
+        if (rc != ISING_OK) return rc;
+    }
+    Engine& e = g_engines[dev];
+    std::lock_guard<std::mutex> g(e.mu);
+    hipError_t r = init_engine(e);
+    if (r == hipSuccess) r = ensure_capacity(e, count);
+    if (r != hipSuccess) {
+        (void)hipGetLastError();
+        return r == hipErrorOutOfMemory ? ISING_ENOMEM : ISING_EDEVICE;
+    }
+    if (e.staged_pending) {  // pinned staging area still being read by the last copy
+        if (hipEventSynchronize(e.staged) != hipSuccess) return ISING_EDEVICE;
+        e.staged_pending = false;
+    }
+    std::vector<uint64_t> work(count);
+    uint32_t live = 0;
+    for (size_t k = 0; k < count; ++k) {
+        ising_ctx* c = ctxs[k];
+        const Planes pl = ctx_planes(c);
+        BatchItem& it = e.h_items[k];
+        it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
+        it.p1 = reinterpret_cast<uint32_t*>(pl.p[1]);
+        it.series = c->series + 2 * c->series_len;
+        it.L = c->L;
+        it.Hw = c->L / 8u;
+        it.cw = (it.Hw % 4u == 0u) ? 4u : (it.Hw % 2u == 0u) ? 2u : 1u;
+        it.t0 = (uint32_t)c->t;
+        it.n = (uint32_t)n[k];
+        it.k0 = (uint32_t)c->p.seed;
+        it.k1 = (uint32_t)(c->p.seed >> 32);
+        it.exact = c->exact ? 1u : 0u;
+        it.table = c->table;
+        work[k] = (uint64_t)c->L * c->L * n[k];
+        if (n[k]) ++live;
+    }
+    // longest work first; lattices with no sweeps are left out of the queue
+    std::vector<uint32_t> idx(count);
+    std::iota(idx.begin(), idx.end(), 0u);
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
+    for (size_t k = 0; k < count; ++k) e.h_order[k] = idx[k];
+    e.h_hdr->count = live;
+    e.h_hdr->head = 0;
+    if (live == 0) return ISING_OK;
+
+    // order the launch after every context's earlier work
+    for (size_t k = 0; k < count; ++k) {
+        hipStream_t cs = ctxs[k]->stream;
+        if (cs == s) continue;
+        if (hipEventRecord(e.order_ev, cs) != hipSuccess || hipStreamWaitEvent(s, e.order_ev, 0) != hipSuccess)
+            return ctx_fail(ctxs[k], hipErrorUnknown);
+    }
+    // the device descriptors may still be read by the previous launch
+    if (e.launched && hipStreamWaitEvent(s, e.done, 0) != hipSuccess) return ctx_fail(ctxs[0], hipErrorUnknown);
+    if (hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(e.staged, s) != hipSuccess)
+        return ctx_fail(ctxs[0], hipErrorUnknown);
+    e.staged_pending = true;
+    r = ensure_graph(e, s);
+    if (r == hipSuccess) r = hipGraphLaunch(e.exec, s);
+    if (r == hipSuccess) r = hipEventRecord(e.done, s);
+    if (r != hipSuccess) return ctx_fail(ctxs[0], r);
+    e.launched = true;
+    // and every context's later work after it
+    for (size_t k = 0; k < count; ++k) {
+        hipStream_t cs = ctxs[k]->stream;
+        if (cs == s) continue;
+        if (hipEventRecord(e.order_ev, s) != hipSuccess || hipStreamWaitEvent(cs, e.order_ev, 0) != hipSuccess)
+            return ctx_fail(ctxs[k], hipErrorUnknown);
+    }
+    for (size_t k = 0; k < count; ++k) {
+        ctxs[k]->t += n[k];
+        ctxs[k]->series_len += n[k];
+    }
+    return ISING_OK;
+}

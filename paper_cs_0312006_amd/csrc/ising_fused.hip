@@ -1,0 +1,298 @@
+// Fused one-pass sweep: both colours of sweep t in one launch, reading the
+// lattice of sweep t-1 from `src` and writing sweep t to `dst` (ping-pong),
+// so the lattice crosses HBM once per sweep (2 bytes per site update).
+//
+// Work unit: one wave owns a tile of R rows by 64*CW words of a plane row
+// (lane l holds words X0 + l*CW .. X0 + l*CW + CW-1). It walks down the
+// tile computing, at row i, colour 0 of row i+1 and then colour 1 of row i,
+// which needs the new colour 0 of rows i-1, i, i+1 (Section 2.2's order:
+// all of colour 0, then all of colour 1; sites of one colour are
+// independent, so any order within a colour gives the same lattice).
+//   - Same-row neighbours across lanes come from the adjacent lane (DPP
+//     wave shift). Across the tile's left/right edge, old colour-1 words are
+//     read from memory; the new colour-0 word just outside the tile is
+//     recomputed up front for all R rows at once (one row per lane).
+//   - Above and below the tile, the new colour-0 rows r0-1 and r0+R are
+//     recomputed (two extra row updates per tile).
+// Recomputed sites use the same counter-based draws as their owners, so the
+// result is bit-identical to any other schedule of the same sweep.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+namespace {
+
+// DPP controls (GFX9): whole-wave shift by one lane.
+constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l+1
+constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l-1
+
+// lane l gets v of lane l+1; lane 63 gets `edge`.
+__device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShl1, 0xf, 0xf, false);
+}
+// lane l gets v of lane l-1; lane 0 gets `edge`.
+__device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShr1, 0xf, 0xf, false);
+}
+
+template <int CW>
+struct Row {
+    uint32_t v[CW];
+};
+
+template <int CW>
+__device__ __forceinline__ Row<CW> ld(const uint32_t* __restrict__ p) {
+    Row<CW> r;
+    if constexpr (CW == 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+    } else if constexpr (CW == 2) {
+        const uint2 x = *reinterpret_cast<const uint2*>(p);
+        r.v[0] = x.x; r.v[1] = x.y;
+    } else {
+#pragma unroll
+        for (int w = 0; w < CW; ++w) r.v[w] = p[w];
+    }
+    return r;
+}
+
+template <int CW>
+__device__ __forceinline__ void st(uint32_t* __restrict__ p, const Row<CW>& r) {
+    if constexpr (CW == 4) {
+        *reinterpret_cast<uint4*>(p) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else if constexpr (CW == 2) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(r.v[0], r.v[1]);
+    } else {
+#pragma unroll
+        for (int w = 0; w < CW; ++w) p[w] = r.v[w];
+    }
+}
+
+// Update one lane's CW words of a plane row. P = (i + c) & 1 selects the
+// same-row neighbour side; `edge` is the word just outside the tile on that
+// side (right for P == 1, left for P == 0) of the `same` row.
+template <int CW, bool EXACT, int P, bool OBS>
+__device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>& own, const Row<CW>& up,
+                                              const Row<CW>& dn, const Row<CW>& same, uint32_t edge,
+                                              uint32_t q0, uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
+                                              uint32_t& sad) {
+    const uint32_t nb = P ? from_right(same.v[0], edge) : from_left(same.v[CW - 1], edge);
+    Row<CW> out;
+#pragma unroll
+    for (int w = 0; w < CW; ++w) {
+        uint32_t S;
+        if (P) {
+            const uint32_t nxt = (w + 1 < CW) ? same.v[(w + 1 < CW) ? w + 1 : 0] : nb;
+            S = __builtin_amdgcn_alignbyte(nxt, same.v[w], 1);
+        } else {
+            const uint32_t prv = (w > 0) ? same.v[(w > 0) ? w - 1 : 0] : nb;
+            S = __builtin_amdgcn_alignbyte(same.v[w], prv, 3);
+        }
+        const uint32_t n = up.v[w] + dn.v[w] + same.v[w] + S;
+        const uint4 r = philox(q0 + (uint32_t)w, t, c, 0u, k0, k1);
+        const uint32_t Wn = own.v[w] ^ flip_mask<EXACT>(lt, own.v[w], n, r);
+        out.v[w] = Wn;
+        if (OBS) sad = sad_misaligned(Wn, n, sad);
+    }
+    return out;
+}
+
+template <int CW>
+__device__ __forceinline__ uint32_t popc(const Row<CW>& r) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int w = 0; w < CW; ++w) s += __builtin_popcount(r.v[w]);
+    return s;
+}
+
+__device__ __forceinline__ uint32_t wrap_row(int i, uint32_t L) {
+    return (uint32_t)(i < 0 ? i + (int)L : (i >= (int)L ? i - (int)L : i));
+}
+
+__device__ __forceinline__ uint32_t xcd_block_f(uint32_t nblocks) {
+    const uint32_t b = blockIdx.x;
+    if ((nblocks & 7u) != 0u) return b;
+    return (b & 7u) * (nblocks >> 3) + (b >> 3);
+}
+
+}  // namespace
+
+template <int CW, int R, bool EXACT>
+__global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, PartialReduce red) {
+    __shared__ LdsTable lt;
+    load_table(lt, at);
+    __syncthreads();
+    const uint32_t lblock = xcd_block_f(gridDim.x);
+    if (lblock == 0) reduce_partials(red);
+
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t tile = lblock * 4u + (threadIdx.x >> 6);
+    if (tile >= a.n_tiles) return;  // whole wave
+    const uint32_t L = a.L, Hw = a.Hw, t = a.t, k0 = a.k0, k1 = a.k1;
+    const uint32_t tx = tile % a.n_tx, ty = tile / a.n_tx;
+    const uint32_t X0 = tx * 64u * CW;
+    const uint32_t x = X0 + lane * CW;
+    const int r0 = (int)(ty * R);
+    const uint32_t xl = X0 == 0 ? Hw - 1 : X0 - 1;
+    const uint32_t xr = X0 + 64u * CW == Hw ? 0u : X0 + 64u * CW;
+    const uint32_t* __restrict__ s0 = a.src0;
+    const uint32_t* __restrict__ s1 = a.src1;
+    uint32_t* __restrict__ d0 = a.dst0;
+    uint32_t* __restrict__ d1 = a.dst1;
+
+    auto row_ptr = [&](const uint32_t* base, int i) { return base + (size_t)wrap_row(i, L) * Hw; };
+    auto out_ptr = [&](uint32_t* base, int i) { return base + (size_t)wrap_row(i, L) * Hw; };
+
+    // Old colour-1 word just outside the tile that the colour-0 update of
+    // row j = r0 + 1 + lane needs: right of the tile for odd j, left for even j.
+    uint32_t edge_c1 = 0;
+    if (lane < (uint32_t)R) {
+        const int j = r0 + 1 + (int)lane;
+        const uint32_t rj = wrap_row(j, L);
+        edge_c1 = row_ptr(s1, j)[(rj & 1u) ? xr : xl];
+    }
+
+    // New colour-0 word just outside the tile for row i = r0 + lane: the
+    // right neighbour word for even i (its byte 0 is needed), the left one
+    // for odd i (its byte 3).
+    uint32_t edge_c0 = 0;
+    if (lane < (uint32_t)R) {
+        const int i = r0 + (int)lane;
+        const uint32_t ri = wrap_row(i, L);
+        const uint32_t xe = (ri & 1u) ? xl : xr;
+        const uint32_t pe = ri & 1u;  // same-row side for colour 0 at row i
+        const uint32_t xn = pe ? (xe + 1 == Hw ? 0u : xe + 1) : (xe == 0 ? Hw - 1 : xe - 1);
+        const uint32_t own = row_ptr(s0, i)[xe];
+        const uint32_t up = row_ptr(s1, i - 1)[xe];
+        const uint32_t dn = row_ptr(s1, i + 1)[xe];
+        const uint32_t same = row_ptr(s1, i)[xe];
+        const uint32_t nbw = row_ptr(s1, i)[xn];
+        const uint32_t S = pe ? __builtin_amdgcn_alignbyte(nbw, same, 1) : __builtin_amdgcn_alignbyte(same, nbw, 3);
+        const uint32_t n = up + dn + same + S;
+        const uint4 r = philox(ri * Hw + xe, t, 0u, 0u, k0, k1);
+        edge_c0 = own ^ flip_mask<EXACT>(lt, own, n, r);
+    }
+
+    uint32_t sad = 0, ups = 0, dummy = 0;
+    // Ring buffers, indexed by compile-time slots in a loop unrolled by 4,
+    // so that a prefetched row is never copied between registers (a copy
+    // would force a wait on the load):
+    //   c1[(row - r0) & 3]      old colour-1 rows
+    //   c0o[(row - r0) & 1]     old colour-0 rows
+    //   c0n[(row - r0 + 1) & 3] new colour-0 rows
+    Row<CW> c1[4], c0o[2], c0n[4];
+    const Row<CW> c1m2 = ld<CW>(row_ptr(s1, r0 - 2) + x);
+    const Row<CW> c1m1 = ld<CW>(row_ptr(s1, r0 - 1) + x);
+    c1[0] = ld<CW>(row_ptr(s1, r0) + x);
+    c1[1] = ld<CW>(row_ptr(s1, r0 + 1) + x);
+    c1[2] = ld<CW>(row_ptr(s1, r0 + 2) + x);
+    const Row<CW> c0om1 = ld<CW>(row_ptr(s0, r0 - 1) + x);
+    c0o[0] = ld<CW>(row_ptr(s0, r0) + x);
+    c0o[1] = ld<CW>(row_ptr(s0, r0 + 1) + x);
+    const uint32_t eR = row_ptr(s1, r0 - 1)[xr];
+    const uint32_t eL = row_ptr(s1, r0)[xl];
+    // new colour-0 rows r0-1 (odd: same-row side P = 1) and r0 (even: P = 0)
+    c0n[0] = update_row<CW, EXACT, 1, false>(lt, c0om1, c1m2, c1[0], c1m1, eR, wrap_row(r0 - 1, L) * Hw + x, t,
+                                             0u, k0, k1, dummy);
+    c0n[1] = update_row<CW, EXACT, 0, false>(lt, c0o[0], c1m1, c1[1], c1[0], eL, wrap_row(r0, L) * Hw + x, t, 0u,
+                                             k0, k1, dummy);
+    st<CW>(out_ptr(d0, r0) + x, c0n[1]);
+
+#pragma unroll 1
+    for (int k = 0; k < R; k += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = r0 + k + u;
+            // prefetch old colour-1 row i+3 and old colour-0 row i+2 into the
+            // slots of rows i-1 and i, which this step no longer reads
+            c1[(u + 3) & 3] = ld<CW>(row_ptr(s1, i + 3) + x);
+            c0o[u & 1] = ld<CW>(row_ptr(s0, i + 2) + x);
+            const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c1, k + u);
+            const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c0, k + u);
+            const uint32_t q1 = wrap_row(i + 1, L) * Hw + x;
+            const uint32_t q0 = wrap_row(i, L) * Hw + x;
+            Row<CW> c1n;
+            if ((u & 1) == 0) {  // i even: both updates have same-row side P = 1
+                c0n[(u + 2) & 3] = update_row<CW, EXACT, 1, false>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                                                                   c1[(u + 1) & 3], e1, q1, t, 0u, k0, k1, dummy);
+                c1n = update_row<CW, EXACT, 1, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3], c0n[(u + 1) & 3],
+                                                     e0, q0, t, 1u, k0, k1, sad);
+            } else {
+                c0n[(u + 2) & 3] = update_row<CW, EXACT, 0, false>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                                                                   c1[(u + 1) & 3], e1, q1, t, 0u, k0, k1, dummy);
+                c1n = update_row<CW, EXACT, 0, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3], c0n[(u + 1) & 3],
+                                                     e0, q0, t, 1u, k0, k1, sad);
+            }
+            if (k + u + 1 < R) st<CW>(out_ptr(d0, i + 1) + x, c0n[(u + 2) & 3]);
+            st<CW>(out_ptr(d1, i) + x, c1n);
+            ups += popc<CW>(c1n) + popc<CW>(c0n[(u + 1) & 3]);
+            // keep the next step's use of this step's prefetch after this
+            // step's work, so the load has a whole step to arrive
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+
+    // per-wave partials: B = 16 * words - 2 * sad, M = 2 * ups - 8 * words
+    const int64_t words = (int64_t)R * CW;
+    int64_t b = 16 * words - 2 * (int64_t)sad;
+    int64_t m = 2 * (int64_t)ups - 8 * words;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        b += __shfl_xor(b, off, 64);
+        m += __shfl_xor(m, off, 64);
+    }
+    if (lane == 0) {
+        a.part[2 * tile] = b;
+        a.part[2 * tile + 1] = m;
+    }
+}
+
+// Stand-alone reduction of one sweep's partials (after the last sweep of a call).
+__global__ void __launch_bounds__(256) k_reduce_partials(PartialReduce red) { reduce_partials(red); }
+
+template <int CW, int R, bool EXACT>
+static void launch_fused_t(const FusedArgs& a, const AcceptTable& at, const PartialReduce& red, hipStream_t s) {
+    const uint32_t blocks = (a.n_tiles + 3u) / 4u;
+    k_fused<CW, R, EXACT><<<blocks, 256, 0, s>>>(a, at, red);
+}
+
+bool fused_supported(uint32_t L, uint32_t cw, uint32_t rows) {
+    if (L % 8u != 0u) return false;
+    const uint32_t Hw = L / 8u;
+    if (cw != 1 && cw != 2 && cw != 4) return false;
+    if (rows != 8 && rows != 16 && rows != 32 && rows != 64) return false;
+    return Hw % (64u * cw) == 0u && L % rows == 0u && L >= 4u;
+}
+
+uint32_t fused_tiles(uint32_t L, uint32_t cw, uint32_t rows) {
+    return (L / 8u / (64u * cw)) * (L / rows);
+}
+
+hipError_t launch_fused(const FusedArgs& a, const AcceptTable& at, bool exact, uint32_t cw, uint32_t rows,
+                        const PartialReduce& red, hipStream_t s) {
+#define ISING_FUSED_CASE(CWv, Rv)                                       \
+    if (cw == CWv && rows == Rv) {                                      \
+        if (exact)                                                      \
+            launch_fused_t<CWv, Rv, true>(a, at, red, s);               \
+        else                                                            \
+            launch_fused_t<CWv, Rv, false>(a, at, red, s);              \
+        return hipGetLastError();                                       \
+    }
+    ISING_FUSED_CASE(1, 8) ISING_FUSED_CASE(1, 16) ISING_FUSED_CASE(1, 32) ISING_FUSED_CASE(1, 64)
+    ISING_FUSED_CASE(2, 8) ISING_FUSED_CASE(2, 16) ISING_FUSED_CASE(2, 32) ISING_FUSED_CASE(2, 64)
+    ISING_FUSED_CASE(4, 8) ISING_FUSED_CASE(4, 16) ISING_FUSED_CASE(4, 32) ISING_FUSED_CASE(4, 64)
+#undef ISING_FUSED_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_partials(const PartialReduce& red, hipStream_t s) {
+    if (red.n == 0) return hipSuccess;
+    k_reduce_partials<<<1, 256, 0, s>>>(red);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -1,0 +1,115 @@
+// Host-visible launch interface between the runtime (ising_runtime.cpp) and
+// the kernels (ising_kernels.hip, ising_fused.hip, ising_batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+
+namespace ising {
+
+// The two colour planes of one lattice state (see ising_device.hpp).
+struct Planes {
+    uint8_t* p[2];  // plane c: L rows of H bytes
+    uint32_t L;     // side
+    uint32_t H;     // L / 2
+    uint32_t Hw;    // H / 4 (meaningful when L % 8 == 0)
+};
+
+// Arguments of the fused one-pass sweep (ising_fused.hip).
+struct FusedArgs {
+    const uint32_t* src0;  // lattice of sweep t-1, colour planes 0 and 1
+    const uint32_t* src1;
+    uint32_t* dst0;        // lattice of sweep t
+    uint32_t* dst1;
+    uint32_t L, Hw, t, k0, k1;
+    uint32_t n_tx;     // tiles across a plane row
+    uint32_t n_tiles;  // tiles in the lattice (one wave each)
+    int64_t* part;     // 2 int64 per tile: partial (B, M)
+};
+
+// Sum of n per-tile (or per-block) partial (B, M) pairs into dst[0], dst[1].
+struct PartialReduce {
+    const int64_t* part;
+    uint32_t n;
+    int64_t* dst;
+};
+
+// Sum n partial (B, M) pairs into dst (one block; every thread must call).
+__device__ __forceinline__ void reduce_partials(const PartialReduce& red) {
+    if (red.n == 0) return;
+    __shared__ int64_t acc[2][4];
+    int64_t b = 0, m = 0;
+    uint32_t k = threadIdx.x;
+    for (; k + 3 * blockDim.x < red.n; k += 4 * blockDim.x) {  // four loads in flight
+        const int64_t b0 = red.part[2 * k], m0 = red.part[2 * k + 1];
+        const int64_t b1 = red.part[2 * (k + blockDim.x)], m1 = red.part[2 * (k + blockDim.x) + 1];
+        const int64_t b2 = red.part[2 * (k + 2 * blockDim.x)], m2 = red.part[2 * (k + 2 * blockDim.x) + 1];
+        const int64_t b3 = red.part[2 * (k + 3 * blockDim.x)], m3 = red.part[2 * (k + 3 * blockDim.x) + 1];
+        b += (b0 + b1) + (b2 + b3);
+        m += (m0 + m1) + (m2 + m3);
+    }
+    for (; k < red.n; k += blockDim.x) {
+        b += red.part[2 * k];
+        m += red.part[2 * k + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        b += __shfl_xor(b, off, 64);
+        m += __shfl_xor(m, off, 64);
+    }
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        acc[0][wv] = b;
+        acc[1][wv] = m;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t sb = 0, sm = 0;
+        for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) {
+            sb += acc[0][w];
+            sm += acc[1][w];
+        }
+        red.dst[0] = sb;
+        red.dst[1] = sm;
+    }
+}
+
+hipError_t launch_init(const Planes& pl, bool words, uint32_t k0, uint32_t k1, uint64_t pthr, hipStream_t s);
+uint32_t two_pass_blocks(const Planes& pl, uint32_t cw);
+hipError_t launch_two_pass(const Planes& pl, const AcceptTable& at, bool exact, uint32_t cw, uint32_t t,
+                           uint32_t k0, uint32_t k1, int64_t* part, const PartialReduce& red, hipStream_t s);
+hipError_t launch_generic_sweep(const Planes& pl, const AcceptTable& at, bool exact, uint32_t t, uint32_t k0,
+                                uint32_t k1, int64_t* obs, hipStream_t s);
+hipError_t launch_observe(const Planes& pl, int64_t* out, hipStream_t s);
+hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t s);
+bool fused_supported(uint32_t L, uint32_t cw, uint32_t rows);
+uint32_t fused_tiles(uint32_t L, uint32_t cw, uint32_t rows);
+hipError_t launch_fused(const FusedArgs& a, const AcceptTable& at, bool exact, uint32_t cw, uint32_t rows,
+                        const PartialReduce& red, hipStream_t s);
+hipError_t launch_reduce_partials(const PartialReduce& red, hipStream_t s);
+
+// One lattice of a workgroup-resident batch (ising_batch.hip).
+struct BatchItem {
+    uint32_t* p0;       // colour planes, updated in place
+    uint32_t* p1;
+    int64_t* series;    // 2 int64 per sweep, for sweeps t0 .. t0+n-1
+    uint32_t L, Hw, cw, t0, n, k0, k1, exact;
+    AcceptTable table;
+};
+
+struct BatchHeader {
+    uint32_t count;  // items in this launch
+    uint32_t head;   // work-queue position, 0 at launch
+};
+
+hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,
+                        hipStream_t s);
+uint32_t batch_block_threads();
+hipError_t batch_occupancy(int* blocks_per_cu);
+
+hipError_t launch_to_canonical(const Planes& pl, int8_t* out, hipStream_t s);
+hipError_t launch_from_canonical(const Planes& pl, const int8_t* in, hipStream_t s);
+
+}  // namespace ising

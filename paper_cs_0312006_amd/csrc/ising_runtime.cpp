@@ -1,0 +1,681 @@
+// C ABI and host runtime of the gfx950 checkerboard Metropolis engine.
+// The public contract (model, keying, error behaviour) is in include/ising.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "ising.h"
+#include "ising_launch.hpp"
+#include "ising_runtime.hpp"
+
+using namespace ising;
+
+namespace ising {
+
+// Threshold of the Metropolis decision for spin s (+1/-1) with neighbour sum
+// n (Section 2.2, steps 2-4): dE = 2 s (J n + h); accept iff the 32-bit draw
+// u < thr, thr = 2^32 for dE <= 0, else floor(exp(-dE/T) * 2^32). Evaluated
+// in IEEE double in exactly this order, without contraction.
+#pragma clang fp contract(off)
+uint64_t metropolis_threshold(double J, double h, double T, int s, int n) {
+    const double dE = 2.0 * (double)s * (J * (double)n + h);
+    if (dE <= 0.0) return (uint64_t)1 << 32;
+    return (uint64_t)std::floor(std::exp(-dE / T) * 4294967296.0);
+}
+
+void build_accept_table(double J, double h, double T, AcceptTable* at, bool* exact) {
+    std::memset(at, 0, sizeof(*at));
+    bool any_zero = false;
+    for (int sbit = 0; sbit < 2; ++sbit) {
+        for (int nup = 0; nup <= 4; ++nup) {
+            const int code = 8 * sbit + nup;
+            const uint64_t thr = metropolis_threshold(J, h, T, sbit ? 1 : -1, 2 * nup - 4);
+            at->thr_lo[code] = (uint32_t)thr;
+            at->thr_hi[code] = (uint32_t)(thr >> 32);
+            if (thr == 0) any_zero = true;
+            at->thr_m1[code] = thr == 0 ? 0u : (uint32_t)(thr - 1);
+        }
+    }
+    *exact = any_zero;
+}
+
+uint64_t fnv1a64(const uint8_t* p, size_t n) {
+    uint64_t hsh = 0xcbf29ce484222325ull;
+    for (size_t k = 0; k < n; ++k) {
+        hsh ^= p[k];
+        hsh *= 0x100000001b3ull;
+    }
+    return hsh;
+}
+
+static bool valid_params(const ising_params* p) {
+    if (!p) return false;
+    if (p->L < 2 || (p->L & 1u) || p->L > ISING_MAX_L) return false;
+    if (!std::isfinite(p->J) || !std::isfinite(p->h) || !std::isfinite(p->T) || !(p->T > 0.0)) return false;
+    if (!(p->p_up >= 0.0 && p->p_up <= 1.0)) return false;
+    if ((p->flags & 0xffu) > ISING_PLAN_GENERIC) return false;
+    return true;
+}
+
+// Plans remembered by the autotuner, by side.
+static std::mutex g_tuned_mu;
+static std::map<uint32_t, Plan> g_tuned;
+
+// Sides up to this run all their sweeps inside one workgroup by default.
+constexpr uint32_t kResidentMaxL = 128;
+// Fused tiles wanted per launch (one wave each) before a taller/wider tile is used.
+constexpr uint32_t kFusedMinTiles = 4096;
+
+static uint32_t default_cw(uint32_t L) {
+    const uint32_t Hw = L / 8u;
+    return (Hw % 4u == 0u) ? 4u : (Hw % 2u == 0u) ? 2u : 1u;
+}
+
+// Largest fused tile (cw, rows) that still gives kFusedMinTiles tiles, else
+// the one with the most tiles.
+static bool default_fused(uint32_t L, uint32_t* cw_out, uint32_t* rows_out) {
+    static const uint32_t cws[3] = {4, 2, 1};
+    static const uint32_t rs[4] = {64, 32, 16, 8};
+    uint32_t best_tiles = 0, bcw = 0, br = 0;
+    for (uint32_t cw : cws) {
+        for (uint32_t r : rs) {
+            if (!fused_supported(L, cw, r)) continue;
+            const uint32_t tiles = fused_tiles(L, cw, r);
+            if (tiles >= kFusedMinTiles) {
+                *cw_out = cw;
+                *rows_out = r;
+                return true;
+            }
+            if (tiles > best_tiles) {
+                best_tiles = tiles;
+                bcw = cw;
+                br = r;
+            }
+        }
+    }
+    if (!best_tiles) return false;
+    *cw_out = bcw;
+    *rows_out = br;
+    return true;
+}
+
+bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) {
+    Plan pl{};
+    const bool words = (L % 8u) == 0u;
+    switch (kind) {
+        case ISING_PLAN_GENERIC:
+            pl.kind = ISING_PLAN_GENERIC;
+            pl.cw = 1;
+            break;
+        case ISING_PLAN_TWO_PASS:
+        case ISING_PLAN_RESIDENT:
+            if (!words) return false;
+            pl.kind = kind;
+            pl.cw = cw ? cw : default_cw(L);
+            if (pl.cw != 1 && pl.cw != 2 && pl.cw != 4) return false;
+            if ((L / 8u) % pl.cw != 0u) return false;
+            break;
+        case ISING_PLAN_FUSED:
+            pl.kind = ISING_PLAN_FUSED;
+            if (cw == 0 && rows == 0) {
+                if (!default_fused(L, &pl.cw, &pl.rows)) return false;
+            } else {
+                uint32_t dcw = 0, dr = 0;
+                const bool have = default_fused(L, &dcw, &dr);
+                pl.cw = cw ? cw : (have ? dcw : 1);
+                pl.rows = rows ? rows : (have ? dr : 8);
+                if (!fused_supported(L, pl.cw, pl.rows)) return false;
+            }
+            break;
+        case ISING_PLAN_AUTO: {
+            {
+                std::lock_guard<std::mutex> g(g_tuned_mu);
+                auto it = g_tuned.find(L);
+                if (it != g_tuned.end()) {
+                    *out = it->second;
+                    return true;
+                }
+            }
+            if (!words) return plan_for(L, ISING_PLAN_GENERIC, 0, 0, out);
+            if (L <= kResidentMaxL) return plan_for(L, ISING_PLAN_RESIDENT, 0, 0, out);
+            if (plan_for(L, ISING_PLAN_FUSED, 0, 0, out)) return true;
+            return plan_for(L, ISING_PLAN_TWO_PASS, 0, 0, out);
+        }
+        default:
+            return false;
+    }
+    *out = pl;
+    return true;
+}
+
+}  // namespace ising
+
+// ---------------------------------------------------------------------------
+// Context helpers
+// ---------------------------------------------------------------------------
+int ctx_fail(ising_ctx* ctx, hipError_t e) {
+    ctx->poisoned = true;
+    ctx->last_hip = e;
+    return ISING_EDEVICE;
+}
+
+#define HIP_TRY(ctx, expr)                       \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return ctx_fail((ctx), e_); \
+    } while (0)
+
+static int ctx_enter(ising_ctx* ctx) {
+    if (!ctx) return ISING_EINVAL;
+    if (ctx->poisoned) return ISING_ESTATE;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return ctx_fail(ctx, e);
+    return ISING_OK;
+}
+
+static Planes planes_of(uint8_t* base, uint32_t L) {
+    Planes p;
+    const size_t N = (size_t)L * L;
+    p.p[0] = base;
+    p.p[1] = base + N / 2;
+    p.L = L;
+    p.H = L / 2;
+    p.Hw = L / 8;
+    return p;
+}
+
+Planes ctx_planes(const ising_ctx* ctx) { return planes_of(ctx->buf[ctx->cur], ctx->L); }
+Planes ctx_planes_alt(const ising_ctx* ctx) { return planes_of(ctx->buf[ctx->cur ^ 1], ctx->L); }
+
+// Make room for `more` series entries beyond the pending ones.
+int ctx_reserve_series(ising_ctx* ctx, uint64_t more) {
+    const uint64_t need = ctx->series_len + more;
+    if (need <= ctx->series_cap) return ISING_OK;
+    uint64_t cap = ctx->series_cap ? ctx->series_cap : 1024;
+    while (cap < need) cap *= 2;
+    int64_t* fresh = nullptr;
+    if (hipMalloc(&fresh, cap * 2 * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return ISING_ENOMEM;
+    }
+    if (ctx->series_len) {
+        HIP_TRY(ctx, hipMemcpyAsync(fresh, ctx->series, ctx->series_len * 2 * sizeof(int64_t),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->series) (void)hipFree(ctx->series);
+    ctx->series = fresh;
+    ctx->series_cap = cap;
+    return ISING_OK;
+}
+
+// Allocate what the context's plan needs: the second lattice buffer for
+// ping-pong, partial-sum buffers sized to the plan's tiles or blocks.
+int ctx_prepare_plan(ising_ctx* ctx) {
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (ctx->plan.kind == ISING_PLAN_FUSED && !ctx->buf[1]) {
+        if (hipMalloc(&ctx->buf[1], N) != hipSuccess) {
+            (void)hipGetLastError();
+            return ISING_ENOMEM;
+        }
+        ctx->owns_buf[1] = true;
+    }
+    uint32_t need = 0;
+    const Planes pl = ctx_planes(ctx);
+    if (ctx->plan.kind == ISING_PLAN_FUSED) need = fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
+    if (ctx->plan.kind == ISING_PLAN_TWO_PASS) need = two_pass_blocks(pl, ctx->plan.cw);
+    if (need > ctx->part_cap) {
+        for (int k = 0; k < 2; ++k) {
+            if (ctx->part[k]) (void)hipFree(ctx->part[k]);
+            ctx->part[k] = nullptr;
+        }
+        ctx->part_cap = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (hipMalloc(&ctx->part[k], (size_t)need * 2 * sizeof(int64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
+            }
+        }
+        ctx->part_cap = need;
+    }
+    return ISING_OK;
+}
+
+static size_t state_bytes_for(uint32_t L, const Plan& pl) {
+    const size_t N = (size_t)L * L;
+    return pl.kind == ISING_PLAN_FUSED ? 2 * N : N;
+}
+
+// n sweeps of the fused plan; series slots ser[0 .. 2n).
+static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser) {
+    const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
+    const uint32_t L = ctx->L, Hw = L / 8u;
+    const uint32_t cw = ctx->plan.cw, rows = ctx->plan.rows;
+    const uint32_t n_tx = Hw / (64u * cw);
+    const uint32_t n_tiles = fused_tiles(L, cw, rows);
+    for (uint64_t k = 0; k < n; ++k) {
+        const uint32_t t = (uint32_t)(ctx->t + k);
+        const Planes src = ctx_planes(ctx), dst = ctx_planes_alt(ctx);
+        FusedArgs a{reinterpret_cast<const uint32_t*>(src.p[0]), reinterpret_cast<const uint32_t*>(src.p[1]),
+                    reinterpret_cast<uint32_t*>(dst.p[0]), reinterpret_cast<uint32_t*>(dst.p[1]),
+                    L, Hw, t, k0, k1, n_tx, n_tiles, ctx->part[k & 1]};
+        PartialReduce red{nullptr, 0, nullptr};
+        if (k > 0) red = PartialReduce{ctx->part[(k - 1) & 1], n_tiles, ser + 2 * (k - 1)};
+        HIP_TRY(ctx, launch_fused(a, ctx->table, ctx->exact, cw, rows, red, ctx->stream));
+        ctx->cur ^= 1;
+    }
+    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->part[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)},
+                                        ctx->stream));
+    return ISING_OK;
+}
+
+static int sweep_two_pass(ising_ctx* ctx, uint64_t n, int64_t* ser) {
+    const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
+    const Planes pl = ctx_planes(ctx);
+    const uint32_t nb = two_pass_blocks(pl, ctx->plan.cw);
+    for (uint64_t k = 0; k < n; ++k) {
+        const uint32_t t = (uint32_t)(ctx->t + k);
+        PartialReduce red{nullptr, 0, nullptr};
+        if (k > 0) red = PartialReduce{ctx->part[0], nb, ser + 2 * (k - 1)};
+        HIP_TRY(ctx, launch_two_pass(pl, ctx->table, ctx->exact, ctx->plan.cw, t, k0, k1, ctx->part[0], red,
+                                     ctx->stream));
+    }
+    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->part[0], nb, ser + 2 * (n - 1)}, ctx->stream));
+    return ISING_OK;
+}
+
+static int sweep_generic(ising_ctx* ctx, uint64_t n, int64_t* ser) {
+    const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
+    HIP_TRY(ctx, launch_zero(ser, 2 * n, ctx->stream));
+    const Planes pl = ctx_planes(ctx);
+    for (uint64_t k = 0; k < n; ++k) {
+        const uint32_t t = (uint32_t)(ctx->t + k);
+        HIP_TRY(ctx, launch_generic_sweep(pl, ctx->table, ctx->exact, t, k0, k1, ser + 2 * k, ctx->stream));
+    }
+    return ISING_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t ising_state_bytes(uint32_t L, uint32_t flags) {
+    if (L < 2 || (L & 1u) || L > ISING_MAX_L) return 0;
+    Plan pl;
+    if (!plan_for(L, flags & 0xffu, 0, 0, &pl)) return 0;
+    return state_bytes_for(L, pl);
+}
+
+static int create_common(const ising_params* params, void* dev_buf, size_t bytes, void* stream,
+                         ising_ctx** out) {
+    if (!out) return ISING_EINVAL;
+    *out = nullptr;
+    if (!valid_params(params)) return ISING_EINVAL;
+    Plan plan;
+    if (!plan_for(params->L, params->flags & 0xffu, 0, 0, &plan)) return ISING_EUNSUPPORTED;
+    const size_t N = (size_t)params->L * params->L;
+    const size_t need = state_bytes_for(params->L, plan);
+    if (dev_buf && bytes < need) return ISING_EINVAL;
+
+    ising_ctx* ctx = new (std::nothrow) ising_ctx();
+    if (!ctx) return ISING_ENOMEM;
+    ctx->p = *params;
+    ctx->L = params->L;
+    ctx->plan = plan;
+    build_accept_table(params->J, params->h, params->T, &ctx->table, &ctx->exact);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return ISING_EDEVICE;
+    }
+    if (stream) {
+        ctx->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete ctx;
+            return ISING_EDEVICE;
+        }
+        ctx->owns_stream = true;
+    }
+    if (dev_buf) {
+        ctx->buf[0] = (uint8_t*)dev_buf;
+        if (need >= 2 * N) ctx->buf[1] = (uint8_t*)dev_buf + N;
+    } else {
+        if (hipMalloc(&ctx->buf[0], N) != hipSuccess) {
+            (void)hipGetLastError();
+            ising_destroy(ctx);
+            return ISING_ENOMEM;
+        }
+        ctx->owns_buf[0] = true;
+    }
+    if (hipMalloc(&ctx->scratch, 4 * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        ising_destroy(ctx);
+        return ISING_ENOMEM;
+    }
+    int rc = ctx_prepare_plan(ctx);
+    if (rc == ISING_OK) rc = ctx_reserve_series(ctx, 1024);
+    if (rc != ISING_OK) {
+        ising_destroy(ctx);
+        return rc;
+    }
+    const uint64_t pthr = (uint64_t)std::floor(params->p_up * 4294967296.0);
+    if (launch_init(ctx_planes(ctx), (ctx->L % 8u) == 0u, (uint32_t)params->seed,
+                    (uint32_t)(params->seed >> 32), pthr, ctx->stream) != hipSuccess) {
+        ising_destroy(ctx);
+        return ISING_EDEVICE;
+    }
+    *out = ctx;
+    return ISING_OK;
+}
+
+int ising_create(const ising_params* params, void* stream, ising_ctx** out) {
+    return create_common(params, nullptr, 0, stream, out);
+}
+
+int ising_create_in(const ising_params* params, void* dev_buf, size_t bytes, void* stream, ising_ctx** out) {
+    if (!dev_buf) {
+        if (out) *out = nullptr;
+        return ISING_EINVAL;
+    }
+    return create_common(params, dev_buf, bytes, stream, out);
+}
+
+int ising_sweep(ising_ctx* ctx, uint64_t n) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (n == 0) return ISING_OK;
+    if (ctx->t + n > ((uint64_t)1 << 32)) return ISING_ERANGE;
+    if (ctx->plan.kind == ISING_PLAN_RESIDENT) return engine_run(&ctx, &n, 1, ctx->stream);
+    rc = ctx_reserve_series(ctx, n);
+    if (rc != ISING_OK) return rc;
+    int64_t* ser = ctx->series + 2 * ctx->series_len;
+    switch (ctx->plan.kind) {
+        case ISING_PLAN_FUSED: rc = sweep_fused(ctx, n, ser); break;
+        case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser); break;
+        case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, ser); break;
+        default: return ISING_EUNSUPPORTED;
+    }
+    if (rc != ISING_OK) return rc;
+    ctx->t += n;
+    ctx->series_len += n;
+    return ISING_OK;
+}
+
+int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream) {
+    if (!ctxs || !n_sweeps) return ISING_EINVAL;
+    if (count == 0) return ISING_OK;
+    int dev = -1;
+    for (size_t k = 0; k < count; ++k) {
+        ising_ctx* c = ctxs[k];
+        if (!c) return ISING_EINVAL;
+        if (c->poisoned) return ISING_ESTATE;
+        if (c->L % 8u != 0u) return ISING_EUNSUPPORTED;
+        if (c->t + n_sweeps[k] > ((uint64_t)1 << 32)) return ISING_ERANGE;
+        if (dev < 0) dev = c->device;
+        if (c->device != dev) return ISING_EINVAL;
+        for (size_t j = 0; j < k; ++j)
+            if (ctxs[j] == c) return ISING_EINVAL;  // one context may appear once
+    }
+    if (hipSetDevice(dev) != hipSuccess) return ISING_EDEVICE;
+    return engine_run(ctxs, n_sweeps, count, stream ? (hipStream_t)stream : ctxs[0]->stream);
+}
+
+static int ensure_canonical(ising_ctx* ctx) {
+    if (ctx->canon) return ISING_OK;
+    if (hipMalloc(&ctx->canon, (size_t)ctx->L * ctx->L) != hipSuccess) {
+        (void)hipGetLastError();
+        return ISING_ENOMEM;
+    }
+    return ISING_OK;
+}
+
+int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (!host || n < N) return ISING_EINVAL;
+    rc = ensure_canonical(ctx);
+    if (rc != ISING_OK) return rc;
+    HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(host, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISING_OK;
+}
+
+int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (!host || n < N || t > ((uint64_t)1 << 32)) return ISING_EINVAL;
+    for (size_t k = 0; k < N; ++k)
+        if (host[k] != 1 && host[k] != -1) return ISING_EINVAL;
+    rc = ensure_canonical(ctx);
+    if (rc != ISING_OK) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->canon, host, N, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, launch_from_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->t = t;
+    ctx->series_len = 0;
+    return ISING_OK;
+}
+
+int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int64_t* mag_series,
+                      uint64_t capacity, uint32_t want) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (want & ~(ISING_OBS_HASH | ISING_OBS_SERIES)) return ISING_EINVAL;
+    const uint64_t len = ctx->series_len;
+    if ((want & ISING_OBS_SERIES) && (bond_series || mag_series) && capacity < len) return ISING_ERANGE;
+    HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
+    int64_t bm[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->scratch, sizeof(bm), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<int64_t> ser;
+    if ((want & ISING_OBS_SERIES) && len && (bond_series || mag_series)) {
+        try {
+            ser.resize(2 * len);
+        } catch (...) {
+            return ISING_ENOMEM;
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(ser.data(), ctx->series, 2 * len * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    }
+    uint64_t hsh = 0;
+    if (want & ISING_OBS_HASH) {
+        const size_t N = (size_t)ctx->L * ctx->L;
+        rc = ensure_canonical(ctx);
+        if (rc != ISING_OK) return rc;
+        std::vector<uint8_t> bytes;
+        try {
+            bytes.resize(N);
+        } catch (...) {
+            return ISING_ENOMEM;
+        }
+        HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(bytes.data(), ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        hsh = fnv1a64(bytes.data(), N);
+    } else {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (want & ISING_OBS_SERIES) {
+        for (uint64_t k = 0; k < len && !ser.empty(); ++k) {
+            if (bond_series) bond_series[k] = ser[2 * k];
+            if (mag_series) mag_series[k] = ser[2 * k + 1];
+        }
+    }
+    if (out) {
+        const double N = (double)ctx->L * (double)ctx->L;
+        out->sweeps_done = ctx->t;
+        out->bond_sum = bm[0];
+        out->mag_sum = bm[1];
+        out->energy = -ctx->p.J * (double)bm[0] - ctx->p.h * (double)bm[1];
+        out->e_per_site = out->energy / N;
+        out->m_per_site = (double)bm[1] / N;
+        out->lattice_hash = hsh;
+        out->series_len = len;
+    }
+    if (want & ISING_OBS_SERIES) ctx->series_len = 0;
+    return ISING_OK;
+}
+
+int ising_series_averages(const int64_t* bond_series, const int64_t* mag_series, uint64_t n, uint32_t L,
+                          double J, double h, ising_averages* out) {
+    if (!bond_series || !mag_series || !out || n == 0 || L < 2) return ISING_EINVAL;
+    const double N = (double)L * (double)L;
+    double se = 0, se2 = 0, sm = 0, sam = 0, sm2 = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        const double e = (-J * (double)bond_series[k] - h * (double)mag_series[k]) / N;
+        const double m = (double)mag_series[k] / N;
+        se += e;
+        se2 += e * e;
+        sm += m;
+        sam += std::fabs(m);
+        sm2 += m * m;
+    }
+    const double dn = (double)n;
+    out->n = n;
+    out->e = se / dn;
+    out->e2 = se2 / dn;
+    out->m = sm / dn;
+    out->abs_m = sam / dn;
+    out->m2 = sm2 / dn;
+    return ISING_OK;
+}
+
+int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words, uint32_t* rows_per_thread) {
+    if (!ctx) return ISING_EINVAL;
+    if (plan) *plan = ctx->plan.kind;
+    if (chunk_words) *chunk_words = ctx->plan.cw;
+    if (rows_per_thread) *rows_per_thread = ctx->plan.rows;
+    return ISING_OK;
+}
+
+int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (plan == ISING_PLAN_AUTO || plan > ISING_PLAN_GENERIC) return ISING_EINVAL;
+    Plan pl;
+    if (!plan_for(ctx->L, plan, cw, rows, &pl)) return ISING_EUNSUPPORTED;
+    const Plan old = ctx->plan;
+    ctx->plan = pl;
+    rc = ctx_prepare_plan(ctx);
+    if (rc != ISING_OK) ctx->plan = old;
+    return rc;
+}
+
+int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (trial_sweeps == 0) return ISING_EINVAL;
+    const uint32_t L = ctx->L;
+    std::vector<Plan> cands;
+    Plan pl;
+    if (L % 8u != 0u) {
+        plan_for(L, ISING_PLAN_GENERIC, 0, 0, &pl);
+        cands.push_back(pl);
+    } else {
+        static const uint32_t cws[3] = {1, 2, 4};
+        static const uint32_t rs[4] = {8, 16, 32, 64};
+        for (uint32_t cw : cws)
+            for (uint32_t r : rs)
+                if (plan_for(L, ISING_PLAN_FUSED, cw, r, &pl)) cands.push_back(pl);
+        for (uint32_t cw : cws)
+            if (plan_for(L, ISING_PLAN_TWO_PASS, cw, 0, &pl)) cands.push_back(pl);
+        if (L <= 1024 && plan_for(L, ISING_PLAN_RESIDENT, 0, 0, &pl)) cands.push_back(pl);
+    }
+    // scratch context over a copy of the lattice, same table and seed
+    ising_params p = ctx->p;
+    p.flags = ISING_PLAN_GENERIC;
+    ising_ctx* tmp = nullptr;
+    rc = ising_create(&p, ctx->stream, &tmp);
+    if (rc != ISING_OK) return rc;
+    const size_t N = (size_t)L * L;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best_ms = 0.f;
+    Plan best = ctx->plan;
+    bool have = false;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = ISING_EDEVICE;
+    for (size_t k = 0; rc == ISING_OK && k < cands.size(); ++k) {
+        tmp->plan = cands[k];
+        rc = ctx_prepare_plan(tmp);
+        if (rc != ISING_OK) break;
+        if (hipMemcpyAsync(tmp->buf[tmp->cur], ctx->buf[ctx->cur], N, hipMemcpyDeviceToDevice, ctx->stream) !=
+            hipSuccess) {
+            rc = ISING_EDEVICE;
+            break;
+        }
+        tmp->t = ctx->t;
+        tmp->series_len = 0;
+        rc = ising_sweep(tmp, 1);  // warm-up
+        if (rc != ISING_OK) break;
+        tmp->series_len = 0;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = ISING_EDEVICE;
+        if (rc == ISING_OK) rc = ising_sweep(tmp, trial_sweeps);
+        if (rc == ISING_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = ISING_EDEVICE;
+        if (rc == ISING_OK && hipEventSynchronize(e1) != hipSuccess) rc = ISING_EDEVICE;
+        float ms = 0.f;
+        if (rc == ISING_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ISING_EDEVICE;
+        if (rc != ISING_OK) break;
+        tmp->series_len = 0;
+        if (!have || ms < best_ms) {
+            best_ms = ms;
+            best = cands[k];
+            have = true;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ising_destroy(tmp);
+    if (rc != ISING_OK) return rc == ISING_EDEVICE ? ctx_fail(ctx, hipErrorUnknown) : rc;
+    const Plan old = ctx->plan;
+    ctx->plan = best;
+    rc = ctx_prepare_plan(ctx);
+    if (rc != ISING_OK) {
+        ctx->plan = old;
+        return rc;
+    }
+    std::lock_guard<std::mutex> g(g_tuned_mu);
+    g_tuned[L] = best;
+    return ISING_OK;
+}
+
+int ising_destroy(ising_ctx* ctx) {
+    if (!ctx) return ISING_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->owns_buf[k] && ctx->buf[k]) (void)hipFree(ctx->buf[k]);
+        if (ctx->part[k]) (void)hipFree(ctx->part[k]);
+    }
+    if (ctx->series) (void)hipFree(ctx->series);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->canon) (void)hipFree(ctx->canon);
+    if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    (void)hipGetLastError();
+    delete ctx;
+    return ISING_OK;
+}
+
+const char* ising_strerror(int code) {
+    switch (code) {
+        case ISING_OK: return "ok";
+        case ISING_EINVAL: return "invalid argument";
+        case ISING_ENOMEM: return "out of memory";
+        case ISING_EDEVICE: return "HIP device error";
+        case ISING_ERANGE: return "out of range";
+        case ISING_EUNSUPPORTED: return "unsupported by this build";
+        case ISING_ESTATE: return "context poisoned by an earlier device error";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,61 @@
+// Internal runtime state shared by the C ABI implementation files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising.h"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+// How a context runs its sweeps.
+struct Plan {
+    uint32_t kind = ISING_PLAN_TWO_PASS;  // ISING_PLAN_*
+    uint32_t cw = 1;                      // 32-bit words per thread/lane and row
+    uint32_t rows = 0;                    // tile height (fused plan)
+};
+
+uint64_t metropolis_threshold(double J, double h, double T, int s, int n);
+void build_accept_table(double J, double h, double T, AcceptTable* at, bool* exact);
+uint64_t fnv1a64(const uint8_t* p, size_t n);
+
+// Plan that can serve side L for the requested ISING_PLAN_* (cw / rows 0 =
+// default); false if it cannot.
+bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out);
+
+}  // namespace ising
+
+struct ising_ctx {
+    ising_params p{};
+    uint32_t L = 0;
+    ising::Plan plan{};
+    ising::AcceptTable table{};
+    bool exact = false;        // some threshold is 0: use the 64-bit compare
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool owns_stream = false;
+    uint8_t* buf[2] = {nullptr, nullptr};  // lattice buffers (the second only for ping-pong)
+    bool owns_buf[2] = {false, false};
+    int cur = 0;                 // which buffer holds the current lattice
+    int64_t* series = nullptr;   // (B_t, M_t) pairs, series_cap of them
+    uint64_t series_cap = 0;
+    uint64_t series_len = 0;
+    int64_t* part[2] = {nullptr, nullptr};  // per-tile / per-block partials
+    uint32_t part_cap = 0;       // pairs per partial buffer
+    int64_t* scratch = nullptr;  // 4 int64 for observables
+    int8_t* canon = nullptr;     // N bytes, canonical layout staging
+    uint64_t t = 0;              // next sweep index
+    bool poisoned = false;
+    hipError_t last_hip = hipSuccess;
+};
+
+ising::Planes ctx_planes(const ising_ctx* ctx);
+ising::Planes ctx_planes_alt(const ising_ctx* ctx);
+int ctx_reserve_series(ising_ctx* ctx, uint64_t more);
+int ctx_prepare_plan(ising_ctx* ctx);
+int ctx_fail(ising_ctx* ctx, hipError_t e);
+
+// Batch engine (ising_engine.cpp): run items[k] for n[k] sweeps each as one
+// persistent launch on stream s.
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s);

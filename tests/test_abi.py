@@ -1,0 +1,106 @@
+"""CPU-only checks of the C ABI library: it loads, exports every entry point
+include/ising.h declares, and its host-side logic (argument validation,
+sizes, error strings, series averages) behaves as documented. No call here
+reaches a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ising.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w ]+\**\s*\**\b(ising_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_cs_0312006_amd import binding
+    binding.lib()
+    return binding
+
+
+def test_header_declares_the_four_core_calls():
+    names = declared_functions()
+    for core in ("ising_create", "ising_sweep", "ising_observables", "ising_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol(b):
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = b.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in b.SIGNATURES, name
+
+
+def test_state_bytes(b):
+    assert b.ising_state_bytes(64) == 64 * 64
+    assert b.ising_state_bytes(6) == 36
+    assert b.ising_state_bytes(3) == 0
+    assert b.ising_state_bytes(0) == 0
+    assert b.ising_state_bytes(65538) == 0
+    assert b.ising_state_bytes(10, b.ISING_PLAN_TWO_PASS) == 0  # 10 % 8 != 0
+    assert b.ising_state_bytes(16, b.ISING_PLAN_TWO_PASS) == 256
+
+
+@pytest.mark.parametrize("kw", [
+    dict(L=3), dict(L=0), dict(L=1), dict(L=65538), dict(L=64, T=0.0), dict(L=64, T=-1.0),
+    dict(L=64, T=float("nan")), dict(L=64, T=float("inf")), dict(L=64, J=float("nan")),
+    dict(L=64, h=float("inf")), dict(L=64, p_up=-0.1), dict(L=64, p_up=1.5),
+    dict(L=64, p_up=float("nan")), dict(L=64, flags=99),
+])
+def test_create_rejects_invalid_parameters(b, kw):
+    with pytest.raises(b.IsingError) as e:
+        b.ising_create(**kw)
+    assert e.value.code == b.ISING_EINVAL
+
+
+def test_forced_plan_that_cannot_serve_is_unsupported(b):
+    with pytest.raises(b.IsingError) as e:
+        b.ising_create(L=10, flags=b.ISING_PLAN_TWO_PASS)
+    assert e.value.code == b.ISING_EUNSUPPORTED
+
+
+def test_null_handles(b):
+    lib = b.lib()
+    assert lib.ising_sweep(None, 1) == b.ISING_EINVAL
+    assert lib.ising_observables(None, None, None, None, 0, 0) == b.ISING_EINVAL
+    assert lib.ising_copy_spins(None, None, 0) == b.ISING_EINVAL
+    assert lib.ising_destroy(None) == b.ISING_OK
+    assert lib.ising_create(None, None, None) == b.ISING_EINVAL
+    assert lib.ising_create_in(None, None, 0, None, None) == b.ISING_EINVAL
+
+
+def test_strerror(b):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert b.ising_strerror(code)
+    assert b.ising_strerror(-100) == "unknown error"
+
+
+def test_series_averages_match_plain_sums(b):
+    """Host FP64 averages of the integer series (Eq. (1) as a time average),
+    compared with NumPy to 1e-12 relative."""
+    rng = np.random.default_rng(0)
+    L, J, h = 64, 1.0, 0.1
+    N = L * L
+    B = 4 * rng.integers(-N // 2, N // 2, size=5000)
+    M = 2 * rng.integers(-N // 2, N // 2, size=5000)
+    avg = b.ising_series_averages(B, M, L, J, h)
+    E = (-J * B.astype(np.float64) - h * M.astype(np.float64)) / N
+    m = M.astype(np.float64) / N
+    for got, want in ((avg.e, E.mean()), (avg.e2, (E * E).mean()), (avg.m, m.mean()),
+                      (avg.abs_m, np.abs(m).mean()), (avg.m2, (m * m).mean())):
+        assert got == pytest.approx(want, rel=1e-12, abs=1e-15)
+    assert avg.n == 5000
+
+
+def test_series_averages_rejects_empty(b):
+    with pytest.raises(b.IsingError):
+        b.ising_series_averages(np.zeros(0, np.int64), np.zeros(0, np.int64), 8)

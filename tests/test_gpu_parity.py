@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path, called through the C ABI, against the oracle on
+identical seeded inputs. Integer results (every site, every per-sweep bond
+sum and magnetisation, the lattice hash) must agree bit for bit; FP64
+averages to 1e-12 relative."""
+import numpy as np
+import pytest
+
+from paper_cs_0312006_amd import workloads as W
+from tests import gpu_util as G
+from tests import physics
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_cs_0312006_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def o():
+    from oracle import ref
+    orc = ref.Oracle()
+    orc.set_threads(G.host_threads())
+    return orc
+
+
+def test_c0_full_parity(b, o):
+    """64 x 64 at T = 2.269185, seed 1, 1000 sweeps: final lattice, hash and
+    all 1000 (B_t, M_t) bit-exact; FP64 averages within 1e-12."""
+    run = W.C0
+    G.log("C0 64x64 1000 sweeps")
+    g = G.gpu_run(b, run)
+    r = G.oracle_run(o, run)
+    G.assert_same(g, r, "C0")
+    avg = b.ising_series_averages(g["B"], g["M"], run.L, run.J, run.h)
+    N = run.L * run.L
+    E = (-run.J * r["B"].astype(np.float64) - run.h * r["M"].astype(np.float64)) / N
+    m = r["M"].astype(np.float64) / N
+    assert avg.e == pytest.approx(E.mean(), rel=1e-12)
+    assert avg.abs_m == pytest.approx(np.abs(m).mean(), rel=1e-12)
+    assert avg.m2 == pytest.approx((m * m).mean(), rel=1e-12)
+
+
+CASES = [
+    # (L, plan, J, h, T, p_up, seed)
+    (8, "TWO_PASS", 1.0, 0.0, 2.269185, 0.5, 3),
+    (16, "TWO_PASS", 1.0, 0.1, 1.5, 0.5, 4),
+    (24, "TWO_PASS", 1.0, 0.0, 3.5, 0.5, 5),
+    (48, "TWO_PASS", 0.7, -0.2, 2.0, 0.3, 2 ** 40 + 9),
+    (136, "TWO_PASS", 1.0, 0.05, 2.269185, 0.5, 6),
+    (256, "TWO_PASS", 1.0, 0.0, 2.269185, 1.0, 7),
+    (2, "GENERIC", 1.0, 0.3, 1.7, 0.5, 8),
+    (6, "GENERIC", 1.0, 0.0, 2.269185, 0.5, 9),
+    (10, "GENERIC", 1.0, 0.1, 1.2, 0.5, 10),
+    (34, "GENERIC", 1.0, 0.0, 2.269185, 0.5, 11),
+    (64, "GENERIC", 1.0, 0.0, 2.269185, 0.5, 12),
+    # thresholds that are exactly 0 (T tiny) take the 64-bit compare
+    (64, "TWO_PASS", 1.0, 0.0, 0.2, 0.5, 13),
+    (18, "GENERIC", 1.0, 0.0, 0.2, 0.5, 14),
+    # every move accepted
+    (32, "TWO_PASS", 1.0, 0.0, 1e300, 0.5, 15),
+]
+
+
+@pytest.mark.parametrize("L,plan,J,h,T,p_up,seed", CASES)
+def test_small_lattices_all_plans(b, o, L, plan, J, h, T, p_up, seed):
+    run = W.Run(L=L, J=J, h=h, T=T, seed=seed, p_up=p_up, sweeps=40)
+    G.log(f"small L={L} plan={plan} h={h} T={T}")
+    g = G.gpu_run(b, run, plan=getattr(b, "ISING_PLAN_" + plan))
+    r = G.oracle_run(o, run)
+    G.assert_same(g, r, f"L={L} {plan}")
+
+
+def test_chunked_calls_equal_one_call(b, o):
+    run = W.Run(L=128, h=0.05, seed=21, sweeps=60)
+    G.log("chunking 128")
+    g1 = G.gpu_run(b, run)
+    g2 = G.gpu_run(b, run, chunks=[1, 7, 20, 32])
+    G.assert_same(g1, g2, "chunked")
+    G.assert_same(g1, G.oracle_run(o, run), "chunked vs oracle")
+
+
+def test_checkpoint_restore_continues_exactly(b, o):
+    """save after a sweeps, destroy, restore into a fresh context at t = a,
+    continue b sweeps: identical to a + b sweeps in one context."""
+    run = W.Run(L=96, h=0.1, T=2.0, seed=22, sweeps=50)
+    G.log("checkpoint 96")
+    full = G.gpu_run(b, run)
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    b.ising_sweep(ctx, 20)
+    saved = b.ising_copy_spins(ctx, run.L)
+    b.ising_destroy(ctx)
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, 1.0)
+    b.ising_load_spins(ctx, saved, 20)
+    b.ising_sweep(ctx, 30)
+    obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+    spins = b.ising_copy_spins(ctx, run.L)
+    b.ising_destroy(ctx)
+    assert np.array_equal(spins, full["spins"])
+    assert np.array_equal(B, full["B"][20:]) and np.array_equal(M, full["M"][20:])
+    assert obs.sweeps_done == 50 and obs.lattice_hash == full["hash"]
+
+
+def test_load_spins_then_flip_symmetry(b, o):
+    """At h = 0 the run from -s equals the negated run from s (same draws)."""
+    L = 64
+    s0 = W.random_lattice(L, 5)
+    res = []
+    for sign in (1, -1):
+        ctx = b.ising_create(L, 1.0, 0.0, 2.269185, 5, 0.5)
+        b.ising_load_spins(ctx, (sign * s0).astype(np.int8), 0)
+        b.ising_sweep(ctx, 25)
+        _, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        res.append((b.ising_copy_spins(ctx, L), B, M))
+        b.ising_destroy(ctx)
+    assert np.array_equal(res[0][0], -res[1][0])
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], -res[1][2])
+    s = s0.copy()
+    Bo, Mo = o.run(s, 1.0, 0.0, 2.269185, 5, 0, 25)
+    assert np.array_equal(s, res[0][0]) and np.array_equal(Bo, res[0][1])
+
+
+def test_load_spins_rejects_bad_bytes(b):
+    ctx = b.ising_create(16)
+    bad = np.ones((16, 16), dtype=np.int8)
+    bad[3, 4] = 0
+    with pytest.raises(b.IsingError) as e:
+        b.ising_load_spins(ctx, bad, 0)
+    assert e.value.code == b.ISING_EINVAL
+    b.ising_destroy(ctx)
+
+
+def test_sweep_index_limit(b):
+    ctx = b.ising_create(16)
+    b.ising_load_spins(ctx, np.ones((16, 16), dtype=np.int8), 2 ** 32 - 2)
+    b.ising_sweep(ctx, 2)
+    with pytest.raises(b.IsingError) as e:
+        b.ising_sweep(ctx, 1)
+    assert e.value.code == b.ISING_ERANGE
+    b.ising_destroy(ctx)
+
+
+def test_create_in_torch_memory_and_stream(b, o):
+    """The lattice state may live in a PyTorch tensor and run on a PyTorch
+    stream (PyTorch is only memory and stream plumbing here)."""
+    import torch
+    L = 128
+    run = W.Run(L=L, h=0.02, seed=31, sweeps=30)
+    nbytes = b.ising_state_bytes(L)
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    G.log("torch buffer 128")
+    ctx = b.ising_create_in(buf.data_ptr(), nbytes, L, run.J, run.h, run.T, run.seed, run.p_up,
+                            stream=stream.cuda_stream)
+    b.ising_sweep(ctx, run.sweeps)
+    obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+    spins = b.ising_copy_spins(ctx, L)
+    b.ising_destroy(ctx)
+    G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, run), "torch")
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_c1_4096_parity_short(b, o, k):
+    """4096 x 4096 at T in {1.5, 2.269185, 3.5}, seed 7: the first 100 sweeps
+    bit-exact against the full oracle."""
+    run = W.C1[k]
+    G.log(f"C1 4096 T={run.T} 100 sweeps")
+    g = G.gpu_run(b, run, sweeps=100)
+    r = G.oracle_run(o, run, sweeps=100)
+    G.assert_same(g, r, f"C1 T={run.T}")
+
+
+def _check_invariants(B, M, L):
+    N = L * L
+    assert np.all(M % 2 == 0) and np.all(B % 4 == 0)
+    assert np.all(np.abs(B) <= 2 * N) and np.all(np.abs(M) <= N)
+
+
+def _check_windows(o, run, spins, sweeps, corners, W_extra=16):
+    """Light-cone check of sampled sites: the oracle evolves a window of
+    side 4*sweeps + W_extra around each corner with global keying; its exact
+    core must equal the GPU lattice there."""
+    Wd = 4 * sweeps + W_extra
+    L = run.L
+    checked = 0
+    for (i0, j0) in corners:
+        win = o.init_window(L, run.seed, run.p_up, i0, j0, Wd)
+        win, valid = o.window_run(L, run.J, run.h, run.T, run.seed, 0, sweeps, i0, j0, win)
+        rows = (np.arange(Wd) + i0) % L
+        cols = (np.arange(Wd) + j0) % L
+        truth = spins[np.ix_(rows, cols)]
+        assert valid.sum() > 0
+        bad = np.argwhere((win != truth) & valid)
+        assert len(bad) == 0, f"window {(i0, j0)}: {len(bad)} sites differ"
+        checked += int(valid.sum())
+    return checked
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_c1_4096_full_length(b, o, k):
+    """All 2000 sweeps: integer invariants every sweep, the last (B, M) and
+    the hash equal to the oracle's of the final lattice, and sampled sites of
+    the last 60 sweeps exact through their light cone (restarted from the
+    lattice the GPU held at sweep 1940)."""
+    run = W.C1[k]
+    G.log(f"C1 4096 T={run.T} 2000 sweeps")
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    b.ising_sweep(ctx, 1940)
+    mid = b.ising_copy_spins(ctx, run.L)
+    b.ising_sweep(ctx, 60)
+    obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+    spins = b.ising_copy_spins(ctx, run.L)
+    b.ising_destroy(ctx)
+    assert len(B) == 2000
+    _check_invariants(B, M, run.L)
+    assert (int(B[-1]), int(M[-1])) == o.observables(spins)
+    assert obs.lattice_hash == o.fnv1a64(spins)
+    # sampled exactness of the last 60 sweeps, restarted from the checkpoint
+    Wd = 4 * 60 + 16
+    for (i0, j0) in [(0, 0), (4096 - 100, 1234), (2000, 4096 - 50)]:
+        rows = (np.arange(Wd) + i0) % run.L
+        cols = (np.arange(Wd) + j0) % run.L
+        win = np.ascontiguousarray(mid[np.ix_(rows, cols)])
+        win, valid = o.window_run(run.L, run.J, run.h, run.T, run.seed, 1940, 60, i0, j0, win)
+        assert not np.any((win != spins[np.ix_(rows, cols)]) & valid)
+        assert valid.sum() >= 16 * 16
+    # physics: the disordered phase equilibrates quickly; at T_c the energy
+    # per site approaches the exact finite-lattice (Kaufman) value
+    e = -B[1000:] / run.L ** 2
+    if run.T > 3.0:
+        assert abs(e.mean() - physics.onsager_energy(run.T)) < 2e-3
+    elif run.T == W.T_C_CONFIG:
+        assert abs(e.mean() - physics.kaufman_energy(run.L, run.T)) < 0.03
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_c2_32768_sampled(b, o, k):
+    """32768 x 32768 (1 GiB), 500 sweeps, for h in {0, 0.1} x {cold, hot}:
+    sampled sites exact through their light cone (window side 2016, one of
+    them wrapping round the periodic corner), the last (B, M) equal to the
+    oracle's observables of the whole final lattice, invariants every sweep."""
+    run = W.C2[k]
+    G.log(f"C2 32768 h={run.h} p_up={run.p_up} 500 sweeps")
+    g = G.gpu_run(b, run)
+    _check_invariants(g["B"], g["M"], run.L)
+    assert (int(g["B"][-1]), int(g["M"][-1])) == o.observables(g["spins"])
+    corners = [(32768 - 1000, 32768 - 1000), (12345, 20000)]
+    G.log(f"C2 window checks h={run.h} p_up={run.p_up}")
+    checked = _check_windows(o, run, g["spins"], run.sweeps, corners)
+    assert checked >= 2 * 16 * 16
