@@ -1,0 +1,304 @@
+"""Benchmark of the checkerboard Metropolis engine on one MI355X.
+
+One step is one full sweep (colour 0, colour 1, per-sweep bond sum and
+magnetisation) of a 32768 x 32768 lattice at T = 2.269185, J = 1, h = 0, hot
+start with seed 11; the lattice (1 GiB of int8 spins in colour planes) is
+resident in HBM before the timed region. Prints one JSON line.
+
+Also reported: the other three 32768^2 runs (h = 0.1, cold starts), the
+batched configuration (1024 lattices of uneven size in one persistent
+launch, against one launch per lattice on a sample), the oracle timed on the
+host cores (cpu_baseline), and roofline figures for the dominant kernel.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit ops)
+
+# Figures measured with rocprofv3 for the fused kernel as built from these
+# sources (profiles/k_fused_ising2d_32768.md). They are reported only while
+# the kernel sources hash to the recorded value; otherwise they are null.
+PROFILED = {
+    "sources_sha256_16": "8ab160f9dd0d74c3",
+    "kernel": "k_fused<4,32>",
+    "hbm_bytes_per_launch": 1393929.0 * 1024 + 1048847.0 * 1024,  # FETCH x2.0 + WRITE x1.0
+    "valu_lane_ops_per_attempt": 16.54,
+    "valu_busy_rocprof": 0.96,
+}
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ising_fused.hip", "ising_device.hpp", "ising_launch.hpp"):
+        with open(os.path.join(ROOT, "paper_cs_0312006_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def host_cores():
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None):
+    """Returns dict with timing, plan and the series of the first sweeps."""
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
+    try:
+        # first sweeps from the initial state, kept for the oracle cross-check
+        b.ising_sweep(ctx, 2)
+        _, B0, M0 = b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        if force:
+            b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, force[0], force[1])
+        elif tune:
+            b.ising_tune(ctx, 4)
+        plan = b.ising_plan_info(ctx)
+        if warmup:
+            b.ising_sweep(ctx, warmup)
+        b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t_host0 = time.perf_counter()
+        e0.record(stream)
+        b.ising_sweep(ctx, steps)
+        e1.record(stream)
+        e1.synchronize()
+        torch.cuda.synchronize()
+        host_s = time.perf_counter() - t_host0
+        ms = e0.elapsed_time(e1)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES)
+    finally:
+        b.ising_destroy(ctx)
+    return {"ms": ms, "host_s": host_s, "plan": plan, "B0": B0, "M0": M0, "B": B, "M": M, "obs": obs}
+
+
+def cpu_baseline(run, sweeps, B0, M0):
+    """The oracle (plain C, OpenMP over rows) on the host cores: initial
+    state plus `sweeps` sweeps of the same lattice; its series must equal
+    the GPU's first sweeps."""
+    from oracle import ref
+    o = ref.Oracle()
+    cores = min(16, host_cores())
+    o.set_threads(cores)
+    t0 = time.perf_counter()
+    s = o.init(run.L, run.seed, run.p_up)
+    t1 = time.perf_counter()
+    B, M = o.run(s, run.J, run.h, run.T, run.seed, 0, sweeps)
+    t2 = time.perf_counter()
+    attempts = run.L * run.L * sweeps
+    parity = bool((list(B) == list(B0[:sweeps])) and (list(M) == list(M0[:sweeps])))
+    del s
+    return {
+        "value": attempts / (t2 - t1) / 1e9,
+        "unit": "spin-update attempts/ns",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{sweeps} sweeps of the {run.L}x{run.L} lattice from its initial state "
+                  f"(init {t1 - t0:.1f} s not counted); series equal to the GPU's: {parity}",
+    }, parity
+
+
+def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
+    """1024 lattices (L = 32 + 16 U{0..62}, T ~ U[1.5, 3.5], h = 0, seed =
+    index) in one persistent launch; comparator: one sweep call per lattice
+    on a random sample, back to back on one stream."""
+    import numpy as np
+    from paper_cs_0312006_amd import workloads as W
+    runs = W.batched(count=count, sweeps=sweeps)
+    total = sum(r.attempts() for r in runs)
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=stream.cuda_stream) for r in runs]
+    try:
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], plan, stream=stream.cuda_stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        hashes = {}
+        for k in range(min(64, len(runs))):
+            obs, _, _ = b.ising_observables(ctxs[k], b.ISING_OBS_HASH | b.ISING_OBS_SERIES)
+            hashes[k] = obs.lattice_hash
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
+    res = {"lattices": count, "sweeps": sweeps, "attempts": total,
+           "value": total / ms / 1e6, "unit": "spin-update attempts/ns", "ms": ms,
+           "plan": {0: "auto", 1: "resident", 2: "stepped"}[plan]}
+    if sample <= 0:
+        return res, hashes
+    # comparator on the first `sample` lattices (the generator's order is random)
+    sub = runs[:sample]
+    sub_attempts = sum(r.attempts() for r in sub)
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=stream.cuda_stream) for r in sub]
+    same = True
+    try:
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for c, r in zip(ctxs, sub):
+            b.ising_sweep(c, r.sweeps)
+        e1.record(stream)
+        e1.synchronize()
+        ms_solo = e0.elapsed_time(e1)
+        for k, c in enumerate(ctxs):
+            obs, _, _ = b.ising_observables(c, b.ISING_OBS_HASH | b.ISING_OBS_SERIES)
+            same &= obs.lattice_hash == hashes[k]
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
+    res["one_launch_per_lattice"] = {"lattices": len(sub), "attempts": sub_attempts, "ms": ms_solo,
+                                     "value": sub_attempts / ms_solo / 1e6,
+                                     "results_identical_to_batched": bool(same)}
+    res["speedup_vs_one_launch_per_lattice"] = (total / ms) / (sub_attempts / ms_solo)
+    return res, hashes
+
+
+def run_served(rates, count, epoch_sweeps):
+    """Poisson request streams (L = 64 U{1..32}, T ~ U[1, 4], h in {0, 0.05},
+    sweeps ~ U{1000..20000}, random seeds) through the continuous-batching
+    server; p50/p99 latency from scheduled arrival to result on the host."""
+    from paper_cs_0312006_amd import serve
+    from paper_cs_0312006_amd import workloads as W
+    out = []
+    ex = serve.GpuExecutor(hash_results=False)
+    for rate in [float(x) for x in rates.split(",") if x]:
+        reqs = W.request_stream(rate, count=count)
+        res, stats = serve.serve(reqs, ex, epoch_sweeps=epoch_sweeps)
+        s = serve.summarize(res, stats["makespan_s"])
+        s.update({"rate_per_s": rate, "epochs": stats["epochs"], "epoch_sweeps": epoch_sweeps,
+                  "offered_attempts_per_ns": rate * sum(r.run.attempts() for r in reqs) / len(reqs) / 1e9})
+        out.append(s)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--cw", type=int, default=0, help="force the fused plan with this chunk width")
+    ap.add_argument("--rows", type=int, default=0, help="force the fused plan with this tile height")
+    ap.add_argument("--no-extra", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--batched-sweeps", type=int, default=10000)
+    ap.add_argument("--batched-sample", type=int, default=64)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-rates", type=str, default="100,1000,5000")
+    ap.add_argument("--served-requests", type=int, default=256)
+    ap.add_argument("--epoch-sweeps", type=int, default=64)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_cs_0312006_amd import binding as b
+    from paper_cs_0312006_amd import workloads as W
+    b.lib()
+    torch.cuda.init()
+    stream = torch.cuda.Stream()
+
+    run = W.C2_HEADLINE
+    force = (args.cw, args.rows) if (args.cw or args.rows) else None
+    head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force)
+    ms, steps = head["ms"], args.steps
+    attempts = run.L * run.L * steps
+    value = attempts / ms / 1e6  # attempts per ns
+    launch_ms = ms / steps      # one fused launch per sweep (plus one tiny reduce per call)
+    plan_names = {1: "two-pass", 2: "fused", 3: "resident", 4: "generic"}
+    plan = head["plan"]
+    alg_bytes = 2.0 * run.L * run.L if plan[0] == 2 else 3.0 * run.L * run.L
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+
+    kname = f"k_fused<{plan[1]},{plan[2]}>" if plan[0] == 2 else "k_two_pass"
+    same_kernel = kernel_sources_hash() == PROFILED["sources_sha256_16"] and kname == PROFILED["kernel"]
+    traffic = PROFILED["hbm_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 if same_kernel else None
+    roof_hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
+                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": launch_ms}
+    roof_alu = None
+    if same_kernel:
+        ops = PROFILED["valu_lane_ops_per_attempt"] * run.L * run.L / (launch_ms * 1e-3)
+        roof_alu = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+                    "unit": "T lane-ops/s (32-bit VALU)", "frac": ops / VALU_PEAK_LANE_OPS, "traffic": traffic,
+                    "traffic_unit": "GB/s", "kernel": kname,
+                    "ops_per_attempt": PROFILED["valu_lane_ops_per_attempt"],
+                    "valu_busy_rocprof": PROFILED["valu_busy_rocprof"], "avg_launch_ms": launch_ms}
+    out = {
+        "metric": "spin-update attempts/ns",
+        "value": value,
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "ising2d 32768x32768 periodic, J=1 h=0 T=2.269185, hot start seed 11",
+                   "L": run.L, "T": run.T, "h": run.h, "p_up": run.p_up, "seed": run.seed,
+                   "step": "one full sweep (both colours) with per-sweep B and M",
+                   "plan": {"kind": plan_names.get(plan[0], str(plan[0])), "chunk_words": plan[1],
+                            "tile_rows": plan[2]}},
+        "roofline": roof_alu if roof_alu else roof_hbm,
+        "roofline_hbm": roof_hbm,
+        "hbm_roof_fraction_at_2B_per_attempt": value / 4000.0,
+        "host_wall_s": head["host_s"],
+    }
+
+    if not args.no_cpu:
+        cpu, parity = cpu_baseline(run, args.cpu_sweeps, head["B0"], head["M0"])
+        out["cpu_baseline"] = cpu
+        out["parity_first_sweeps_vs_oracle"] = parity
+
+    if not args.no_extra:
+        extra = []
+        for r in W.C2:
+            if r == run:
+                continue
+            h = run_headline(b, torch, stream, r, steps, args.warmup, tune=False)
+            extra.append({"h": r.h, "p_up": r.p_up, "sweeps": steps,
+                          "value": r.L * r.L * steps / h["ms"] / 1e6, "unit": "attempts/ns"})
+        out["c2_other_runs"] = extra
+        stepped, h_st = run_batched(b, torch, stream, 1024, args.batched_sweeps, args.batched_sample, plan=2)
+        resident, h_re = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=1)
+        stepped["resident_plan_same_config"] = {"value": resident["value"], "ms": resident["ms"],
+                                                "results_identical": h_st == h_re}
+        out["batched"] = stepped
+
+    if not args.no_extra and not args.no_served:
+        out["served"] = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 1 << 30
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

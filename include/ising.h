@@ -167,6 +167,20 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * Asynchronous; the contexts' own streams are ordered after it. */
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream);
 
+/* As ising_sweep_batch with an explicit batch plan:
+ * ISING_BATCH_RESIDENT: one persistent launch, each workgroup runs whole
+ *   lattices (every sweep) taken from a work queue, largest first;
+ * ISING_BATCH_STEPPED: every colour pass is one launch over the chunks of
+ *   all lattices, so each lattice is spread over the whole GPU; sweeps are
+ *   replayed from a captured graph in groups of 16;
+ * ISING_BATCH_AUTO: resident when every side is <= 256, else stepped.
+ * Results are identical for every plan. */
+#define ISING_BATCH_AUTO 0u
+#define ISING_BATCH_RESIDENT 1u
+#define ISING_BATCH_STEPPED 2u
+int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream,
+                           uint32_t plan);
+
 /* Plain time averages of a series window of n sweeps for an L x L lattice
  * with coupling J and field h (host only, no device work). */
 int ising_series_averages(const int64_t* bond_series, const int64_t* mag_series, uint64_t n,

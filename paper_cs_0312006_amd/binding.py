@@ -29,6 +29,10 @@ ISING_PLAN_FUSED = 2
 ISING_PLAN_RESIDENT = 3
 ISING_PLAN_GENERIC = 4
 
+ISING_BATCH_AUTO = 0
+ISING_BATCH_RESIDENT = 1
+ISING_BATCH_STEPPED = 2
+
 ISING_OBS_HASH = 1
 ISING_OBS_SERIES = 2
 
@@ -68,6 +72,8 @@ SIGNATURES = {
     "ising_copy_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ising_load_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64]),
     "ising_sweep_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p]),
+    "ising_sweep_batch_plan": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p,
+                                         C.c_uint32]),
     "ising_series_averages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_double,
                                         C.c_double, C.POINTER(ising_averages)]),
     "ising_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
@@ -183,6 +189,13 @@ def ising_sweep_batch(ctxs, n_sweeps, stream=None):
     arr = (C.c_void_p * k)(*ctxs)
     ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
     _check(lib().ising_sweep_batch(arr, ns, k, stream), "ising_sweep_batch")
+
+
+def ising_sweep_batch_plan(ctxs, n_sweeps, plan, stream=None):
+    k = len(ctxs)
+    arr = (C.c_void_p * k)(*ctxs)
+    ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
+    _check(lib().ising_sweep_batch_plan(arr, ns, k, stream, int(plan)), "ising_sweep_batch_plan")
 
 
 def ising_series_averages(bond, mag, L, J=1.0, h=0.0):

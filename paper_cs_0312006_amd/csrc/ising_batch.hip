@@ -20,11 +20,11 @@ namespace {
 
 constexpr uint32_t kBatchThreads = 512;
 
-template <int CW, bool OBS, bool EXACT>
-__device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem& it, uint32_t c, uint32_t t,
-                                            uint32_t& sad, uint32_t& ups) {
-    uint32_t* own = c ? it.p1 : it.p0;
-    const uint32_t* oth = c ? it.p0 : it.p1;
+template <int CW, bool OBS, bool EXACT, typename PT>
+__device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem& it, PT p0, PT p1, uint32_t c,
+                                            uint32_t t, uint32_t& sad, uint32_t& ups) {
+    PT own = c ? p1 : p0;
+    PT oth = c ? p0 : p1;
     const uint32_t L = it.L, Hw = it.Hw;
     const uint32_t per_row = Hw / CW;
     const uint32_t total = L * per_row;
@@ -62,16 +62,17 @@ __device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem&
     }
 }
 
-template <int CW, bool EXACT>
-__device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem& it, int64_t (*red)[16]) {
+template <int CW, bool EXACT, typename PT>
+__device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem& it, PT p0, PT p1,
+                                            int64_t (*red)[16]) {
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t nwaves = blockDim.x >> 6;
     for (uint32_t s = 0; s < it.n; ++s) {
         const uint32_t t = it.t0 + s;
         uint32_t sad = 0, ups = 0;
-        colour_pass<CW, false, EXACT>(lt, it, 0u, t, sad, ups);
+        colour_pass<CW, false, EXACT>(lt, it, p0, p1, 0u, t, sad, ups);
         __syncthreads();
-        colour_pass<CW, true, EXACT>(lt, it, 1u, t, sad, ups);
+        colour_pass<CW, true, EXACT>(lt, it, p0, p1, 1u, t, sad, ups);
         // words of colour 1 this thread updated
         const uint32_t total = it.L * (it.Hw / CW);
         const uint32_t mine = threadIdx.x < total ? (total - 1 - threadIdx.x) / blockDim.x + 1 : 0u;
@@ -104,11 +105,23 @@ __device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem&
 
 }  // namespace
 
+// Run all sweeps of one lattice with its planes at p0/p1 (global memory or
+// this workgroup's LDS copy).
+template <bool EXACT, typename PT>
+__device__ __forceinline__ void run_any(const LdsTable& lt, const BatchItem& it, PT p0, PT p1,
+                                        int64_t (*red)[16]) {
+    if (it.cw == 4) run_lattice<4, EXACT>(lt, it, p0, p1, red);
+    else if (it.cw == 2) run_lattice<2, EXACT>(lt, it, p0, p1, red);
+    else run_lattice<1, EXACT>(lt, it, p0, p1, red);
+}
+
 __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __restrict__ items,
                                                          const uint32_t* __restrict__ order, BatchHeader* hdr) {
     __shared__ LdsTable lt;
     __shared__ uint32_t s_slot;
     __shared__ int64_t red[2][16];
+    // lattices of at most kBatchLdsBytes run from this LDS copy
+    __shared__ uint32_t lat[kBatchLdsBytes / 4];
     const uint32_t count = hdr->count;
     for (;;) {
         if (threadIdx.x == 0) s_slot = atomicAdd(&hdr->head, 1u);
@@ -118,14 +131,29 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __rest
         const BatchItem& it = items[order[slot]];
         load_table(lt, it.table);
         __syncthreads();
-        const uint32_t key = it.cw * 2u + it.exact;
-        switch (key) {
-            case 8: run_lattice<4, false>(lt, it, red); break;
-            case 9: run_lattice<4, true>(lt, it, red); break;
-            case 4: run_lattice<2, false>(lt, it, red); break;
-            case 5: run_lattice<2, true>(lt, it, red); break;
-            case 2: run_lattice<1, false>(lt, it, red); break;
-            default: run_lattice<1, true>(lt, it, red); break;
+        const uint32_t plane_words = it.L * it.Hw;
+        if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
+            uint32_t* l0 = lat;
+            uint32_t* l1 = lat + plane_words;
+            const global_u32* g0 = as_global(it.p0);
+            const global_u32* g1 = as_global(it.p1);
+            for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
+                l0[k] = g0[k];
+                l1[k] = g1[k];
+            }
+            __syncthreads();
+            if (it.exact) run_any<true>(lt, it, l0, l1, red);
+            else run_any<false>(lt, it, l0, l1, red);
+            __syncthreads();
+            global_u32* g0w = as_global(it.p0);
+            global_u32* g1w = as_global(it.p1);
+            for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
+                g0w[k] = l0[k];
+                g1w[k] = l1[k];
+            }
+        } else {
+            if (it.exact) run_any<true>(lt, it, as_global(it.p0), as_global(it.p1), red);
+            else run_any<false>(lt, it, as_global(it.p0), as_global(it.p1), red);
         }
         // everyone has read s_slot and the table before they are replaced
         __syncthreads();

@@ -145,4 +145,9 @@ __device__ __forceinline__ uint32_t sad_misaligned(uint32_t Wn, uint32_t n, uint
     return __builtin_amdgcn_sad_u8(Wn << 2, n, acc);
 }
 
+// Pointers read from descriptors in memory are generic; naming the global
+// address space lets the compiler use global (not flat) loads and stores.
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+__device__ __forceinline__ global_u32* as_global(uint32_t* p) { return (global_u32*)p; }
+
 }  // namespace ising

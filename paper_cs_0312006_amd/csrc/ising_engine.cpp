@@ -40,7 +40,17 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0;
+    // stepped plan
+    uint32_t* d_vbs = nullptr;
+    uint32_t* h_vbs = nullptr;
+    MultiHeader* d_mhdr = nullptr;
+    MultiHeader* h_mhdr = nullptr;
+    hipGraph_t mgraph = nullptr;
+    hipGraphExec_t mexec = nullptr;
+    uint32_t mgrid = 0;
 };
+
+constexpr uint32_t kSweepsPerReplay = 16;
 
 constexpr int kMaxDevices = 64;
 Engine g_engines[kMaxDevices];
@@ -50,6 +60,18 @@ void release_buffers(Engine& e) {
     if (e.graph) (void)hipGraphDestroy(e.graph);
     e.exec = nullptr;
     e.graph = nullptr;
+    if (e.mexec) (void)hipGraphExecDestroy(e.mexec);
+    if (e.mgraph) (void)hipGraphDestroy(e.mgraph);
+    e.mexec = nullptr;
+    e.mgraph = nullptr;
+    if (e.d_vbs) (void)hipFree(e.d_vbs);
+    if (e.h_vbs) (void)hipHostFree(e.h_vbs);
+    if (e.d_mhdr) (void)hipFree(e.d_mhdr);
+    if (e.h_mhdr) (void)hipHostFree(e.h_mhdr);
+    e.d_vbs = nullptr;
+    e.h_vbs = nullptr;
+    e.d_mhdr = nullptr;
+    e.h_mhdr = nullptr;
     if (e.d_items) (void)hipFree(e.d_items);
     if (e.d_order) (void)hipFree(e.d_order);
     if (e.d_hdr) (void)hipFree(e.d_hdr);
@@ -84,6 +106,10 @@ hipError_t ensure_capacity(Engine& e, size_t count) {
     if ((r = hipHostMalloc(&e.h_items, cap * sizeof(BatchItem), hipHostMallocDefault)) != hipSuccess) return r;
     if ((r = hipHostMalloc(&e.h_order, cap * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) return r;
     if ((r = hipHostMalloc(&e.h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess) return r;
+    if ((r = hipMalloc(&e.d_vbs, (cap + 1) * sizeof(uint32_t))) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_vbs, (cap + 1) * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) return r;
+    if ((r = hipMalloc(&e.d_mhdr, sizeof(MultiHeader))) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_mhdr, sizeof(MultiHeader), hipHostMallocDefault)) != hipSuccess) return r;
     e.cap = cap;
     return hipSuccess;
 }
@@ -104,6 +130,7 @@ hipError_t init_engine(Engine& e) {
     if ((r = batch_occupancy(&per_cu)) != hipSuccess) return r;
     if (per_cu < 1) per_cu = 1;
     e.grid = (uint32_t)prop.multiProcessorCount * (uint32_t)per_cu;
+    e.mgrid = (uint32_t)prop.multiProcessorCount * 8u;
     e.ready = true;
     return hipSuccess;
 }
@@ -126,9 +153,26 @@ hipError_t ensure_graph(Engine& e, hipStream_t s) {
     return r;
 }
 
+// Capture G sweeps of the stepped plan (one advance node + 2 G passes).
+hipError_t ensure_multi_graph(Engine& e) {
+    if (e.mexec) return hipSuccess;
+    hipStream_t cap = nullptr;
+    hipError_t r = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (r != hipSuccess) return r;
+    r = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (r == hipSuccess) {
+        hipError_t lr = launch_multi_graph_body(e.d_items, e.d_vbs, e.d_mhdr, kSweepsPerReplay, e.mgrid, cap);
+        r = hipStreamEndCapture(cap, &e.mgraph);
+        if (lr != hipSuccess) r = lr;
+    }
+    if (r == hipSuccess) r = hipGraphInstantiate(&e.mexec, e.mgraph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    return r;
+}
+
 }  // namespace
 
-int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s) {
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped) {
     int dev = ctxs[0]->device;
     if (dev < 0 || dev >= kMaxDevices) return ISING_EINVAL;
     // series room first (may synchronise the contexts' streams)
@@ -170,14 +214,30 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         work[k] = (uint64_t)c->L * c->L * n[k];
         if (n[k]) ++live;
     }
-    // longest work first; lattices with no sweeps are left out of the queue
-    std::vector<uint32_t> idx(count);
-    std::iota(idx.begin(), idx.end(), 0u);
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
-    for (size_t k = 0; k < count; ++k) e.h_order[k] = idx[k];
-    e.h_hdr->count = live;
-    e.h_hdr->head = 0;
+    uint64_t max_n = 0;
+    for (size_t k = 0; k < count; ++k) max_n = std::max<uint64_t>(max_n, n[k]);
     if (live == 0) return ISING_OK;
+    if (!stepped) {
+        // longest work first; lattices with no sweeps are left out of the queue
+        std::vector<uint32_t> idx(count);
+        std::iota(idx.begin(), idx.end(), 0u);
+        std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return work[a] > work[b]; });
+        for (size_t k = 0; k < count; ++k) e.h_order[k] = idx[k];
+        e.h_hdr->count = live;
+        e.h_hdr->head = 0;
+    } else {
+        uint64_t vb = 0;
+        for (size_t k = 0; k < count; ++k) {
+            e.h_vbs[k] = (uint32_t)vb;
+            vb += multi_vblocks(e.h_items[k].L, e.h_items[k].cw);
+        }
+        if (vb >= ((uint64_t)1 << 32)) return ISING_ERANGE;
+        e.h_vbs[count] = (uint32_t)vb;
+        e.h_mhdr->n_items = (uint32_t)count;
+        e.h_mhdr->total_vblocks = (uint32_t)vb;
+        e.h_mhdr->s_base = 0u - kSweepsPerReplay;  // the graph's first node adds G
+        e.h_mhdr->pad = 0;
+    }
 
     // order the launch after every context's earlier work
     for (size_t k = 0; k < count; ++k) {
@@ -188,14 +248,30 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     }
     // the device descriptors may still be read by the previous launch
     if (e.launched && hipStreamWaitEvent(s, e.done, 0) != hipSuccess) return ctx_fail(ctxs[0], hipErrorUnknown);
-    if (hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipEventRecord(e.staged, s) != hipSuccess)
-        return ctx_fail(ctxs[0], hipErrorUnknown);
+    bool copied;
+    if (!stepped) {
+        copied = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) ==
+                     hipSuccess &&
+                 hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s) ==
+                     hipSuccess &&
+                 hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s) == hipSuccess;
+    } else {
+        copied = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) ==
+                     hipSuccess &&
+                 hipMemcpyAsync(e.d_vbs, e.h_vbs, (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) ==
+                     hipSuccess &&
+                 hipMemcpyAsync(e.d_mhdr, e.h_mhdr, sizeof(MultiHeader), hipMemcpyHostToDevice, s) == hipSuccess;
+    }
+    if (!copied || hipEventRecord(e.staged, s) != hipSuccess) return ctx_fail(ctxs[0], hipErrorUnknown);
     e.staged_pending = true;
-    r = ensure_graph(e, s);
-    if (r == hipSuccess) r = hipGraphLaunch(e.exec, s);
+    if (!stepped) {
+        r = ensure_graph(e, s);
+        if (r == hipSuccess) r = hipGraphLaunch(e.exec, s);
+    } else {
+        r = ensure_multi_graph(e);
+        const uint64_t replays = (max_n + kSweepsPerReplay - 1) / kSweepsPerReplay;
+        for (uint64_t k = 0; r == hipSuccess && k < replays; ++k) r = hipGraphLaunch(e.mexec, s);
+    }
     if (r == hipSuccess) r = hipEventRecord(e.done, s);
     if (r != hipSuccess) return ctx_fail(ctxs[0], r);
     e.launched = true;

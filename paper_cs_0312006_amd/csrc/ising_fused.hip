@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, Part
     if (lblock == 0) reduce_partials(red);
 
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t tile = lblock * 4u + (threadIdx.x >> 6);
+    // the tile is wave-uniform: keep it (and all row arithmetic) scalar
+    const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)(lblock * 4u + (threadIdx.x >> 6)));
     if (tile >= a.n_tiles) return;  // whole wave
     const uint32_t L = a.L, Hw = a.Hw, t = a.t, k0 = a.k0, k1 = a.k1;
     const uint32_t tx = tile % a.n_tx, ty = tile / a.n_tx;

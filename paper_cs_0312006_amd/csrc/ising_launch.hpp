@@ -104,10 +104,26 @@ struct BatchHeader {
     uint32_t head;   // work-queue position, 0 at launch
 };
 
+// Lattices whose two planes fit in this many bytes run from LDS in the
+// resident batch kernel (256 x 256 sites).
+constexpr uint32_t kBatchLdsBytes = 65536;
+
 hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,
                         hipStream_t s);
 uint32_t batch_block_threads();
 hipError_t batch_occupancy(int* blocks_per_cu);
+
+// Stepped multi-lattice passes (ising_multi.hip).
+struct MultiHeader {
+    uint32_t n_items;        // items in the work list
+    uint32_t total_vblocks;  // virtual blocks over all items
+    uint32_t s_base;         // sweep base; the graph's first node adds G to it
+    uint32_t pad;
+};
+constexpr uint32_t kMultiChunksPerThread = 4;
+uint32_t multi_vblocks(uint32_t L, uint32_t cw);
+hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_start, MultiHeader* hdr,
+                                   uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
 
 hipError_t launch_to_canonical(const Planes& pl, int8_t* out, hipStream_t s);
 hipError_t launch_from_canonical(const Planes& pl, const int8_t* in, hipStream_t s);

@@ -71,6 +71,8 @@ static std::map<uint32_t, Plan> g_tuned;
 
 // Sides up to this run all their sweeps inside one workgroup by default.
 constexpr uint32_t kResidentMaxL = 128;
+// Batches whose largest side is at most this use the resident kernel.
+constexpr uint32_t kResidentBatchMaxL = 256;
 // Fused tiles wanted per launch (one wave each) before a taller/wider tile is used.
 constexpr uint32_t kFusedMinTiles = 4096;
 
@@ -394,7 +396,7 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
     if (rc != ISING_OK) return rc;
     if (n == 0) return ISING_OK;
     if (ctx->t + n > ((uint64_t)1 << 32)) return ISING_ERANGE;
-    if (ctx->plan.kind == ISING_PLAN_RESIDENT) return engine_run(&ctx, &n, 1, ctx->stream);
+    if (ctx->plan.kind == ISING_PLAN_RESIDENT) return engine_run(&ctx, &n, 1, ctx->stream, false);
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
     int64_t* ser = ctx->series + 2 * ctx->series_len;
@@ -411,7 +413,12 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
 }
 
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream) {
-    if (!ctxs || !n_sweeps) return ISING_EINVAL;
+    return ising_sweep_batch_plan(ctxs, n_sweeps, count, stream, ISING_BATCH_AUTO);
+}
+
+int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream,
+                           uint32_t plan) {
+    if (!ctxs || !n_sweeps || plan > ISING_BATCH_STEPPED) return ISING_EINVAL;
     if (count == 0) return ISING_OK;
     int dev = -1;
     for (size_t k = 0; k < count; ++k) {
@@ -426,7 +433,16 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
             if (ctxs[j] == c) return ISING_EINVAL;  // one context may appear once
     }
     if (hipSetDevice(dev) != hipSuccess) return ISING_EDEVICE;
-    return engine_run(ctxs, n_sweeps, count, stream ? (hipStream_t)stream : ctxs[0]->stream);
+    bool stepped = plan == ISING_BATCH_STEPPED;
+    if (plan == ISING_BATCH_AUTO) {
+        // one workgroup per lattice when every lattice is small enough for
+        // a workgroup to sweep it quickly; otherwise spread every lattice
+        // over the whole GPU
+        uint32_t max_l = 0;
+        for (size_t k = 0; k < count; ++k) max_l = std::max(max_l, ctxs[k]->L);
+        stepped = max_l > kResidentBatchMaxL;
+    }
+    return engine_run(ctxs, n_sweeps, count, stream ? (hipStream_t)stream : ctxs[0]->stream, stepped);
 }
 
 static int ensure_canonical(ising_ctx* ctx) {

@@ -56,6 +56,7 @@ int ctx_reserve_series(ising_ctx* ctx, uint64_t more);
 int ctx_prepare_plan(ising_ctx* ctx);
 int ctx_fail(ising_ctx* ctx, hipError_t e);
 
-// Batch engine (ising_engine.cpp): run items[k] for n[k] sweeps each as one
-// persistent launch on stream s.
-int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s);
+// Batch engine (ising_engine.cpp): run ctxs[k] for n[k] sweeps each on
+// stream s, either as one persistent workgroup-resident launch or as the
+// stepped multi-lattice graph.
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped);

@@ -1,0 +1,172 @@
+"""Request server for Ising solves: continuous batching on one GPU.
+
+A request asks for `sweeps` checkerboard Metropolis sweeps of an L x L
+lattice (J, h, T, seed, p_up) and gets back the final lattice hash, the
+final bond sum and magnetisation and FP64 averages of the per-sweep series.
+
+The loop works in epochs. Every request admitted so far advances by up to
+`epoch_sweeps` sweeps in one batched call (`ising_sweep_batch_plan`, the
+stepped plan, which spreads every lattice over the whole GPU). Between
+epochs, requests that have arrived are admitted first come, first served,
+as long as the HBM budget (the sum of the admitted lattices' device bytes)
+and the slot limit allow; requests whose sweeps are done are retired.
+Lattice and draw state stay on the device for a request's whole life.
+Because the draws are keyed by (seed, sweep, colour, site), a request's
+result does not depend on which epochs or which other requests it shared
+the GPU with.
+
+The next epoch is enqueued before the current one is waited for: which
+requests take part and how many sweeps each runs is known in advance, and
+every request has its own stream, so retiring a request waits only for
+the epochs it was part of.
+"""
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+
+@dataclass
+class Result:
+    rid: int
+    L: int
+    sweeps: int
+    arrival: float        # scheduled arrival, seconds after the stream start
+    admitted: float       # when it was admitted
+    done: float           # when its result was on the host
+    lattice_hash: int = 0
+    bond_sum: int = 0
+    mag_sum: int = 0
+    e_mean: float = 0.0   # <E/N> over the second half of the sweeps
+    abs_m_mean: float = 0.0
+    error: str = ""
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+class GpuExecutor:
+    """Executor over the C ABI (one stream per request)."""
+
+    def __init__(self, hash_results=True):
+        from . import binding as b
+        self.b = b
+        b.lib()
+        self.hash_results = hash_results
+
+    def bytes_for(self, run):
+        return self.b.ising_state_bytes(run.L, self.b.ISING_PLAN_TWO_PASS) or run.L * run.L
+
+    def create(self, run):
+        return self.b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, self.b.ISING_PLAN_TWO_PASS)
+
+    def step(self, handles, sweeps):
+        self.b.ising_sweep_batch_plan(handles, sweeps, self.b.ISING_BATCH_STEPPED)
+
+    def result(self, handle, run):
+        b = self.b
+        want = b.ISING_OBS_SERIES | (b.ISING_OBS_HASH if self.hash_results else 0)
+        obs, B, M = b.ising_observables(handle, want)
+        half = len(B) // 2
+        avg = b.ising_series_averages(B[half:], M[half:], run.L, run.J, run.h)
+        return {"lattice_hash": obs.lattice_hash, "bond_sum": obs.bond_sum, "mag_sum": obs.mag_sum,
+                "e_mean": avg.e, "abs_m_mean": avg.abs_m}
+
+    def destroy(self, handle):
+        self.b.ising_destroy(handle)
+
+
+def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=64,
+          clock=time.perf_counter, sleep=time.sleep):
+    """Run a stream of workloads.Request through the executor. Returns
+    (results sorted by request id, stats)."""
+    order = sorted(range(len(requests)), key=lambda k: requests[k].arrival)
+    future = collections.deque(order)          # not yet arrived
+    waiting = collections.deque()              # arrived, not admitted
+    active = {}                                # rid -> [handle, remaining, bytes, admitted]
+    used = 0
+    results = {}
+    epochs = 0
+    t0 = clock()
+    in_flight = None                           # (ids, sweeps) of the enqueued epoch not yet retired
+
+    def now():
+        return clock() - t0
+
+    def admit():
+        nonlocal used
+        t = now()
+        while future and requests[future[0]].arrival <= t:
+            waiting.append(future.popleft())
+        while waiting and len(active) < max_slots:
+            rid = waiting[0]
+            run = requests[rid].run
+            need = executor.bytes_for(run)
+            if need > hbm_budget:   # can never fit: refuse rather than block the queue
+                waiting.popleft()
+                results[rid] = Result(rid, run.L, run.sweeps, requests[rid].arrival, t, t,
+                                      error="larger than the HBM budget")
+                continue
+            if used + need > hbm_budget:
+                break
+            waiting.popleft()
+            active[rid] = [executor.create(run), run.sweeps, need, t]
+            used += need
+
+    def retire(ids, sweeps):
+        nonlocal used
+        for rid, n in zip(ids, sweeps):
+            slot = active[rid]
+            slot[1] -= n
+        finished = [rid for rid in ids if active[rid][1] == 0]
+        for rid in finished:
+            handle, _, need, adm = active.pop(rid)
+            run = requests[rid].run
+            res = executor.result(handle, run)   # waits for this request's last epoch only
+            executor.destroy(handle)
+            used -= need
+            results[rid] = Result(rid, run.L, run.sweeps, requests[rid].arrival, adm, now(), **res)
+
+    while future or waiting or active or in_flight:
+        admit()
+        # the next epoch: every active request not already finishing in the
+        # epoch in flight advances by up to epoch_sweeps
+        pending = {}
+        if in_flight:
+            for rid, n in zip(*in_flight):
+                pending[rid] = n
+        ids, sweeps = [], []
+        for rid, slot in active.items():
+            left = slot[1] - pending.get(rid, 0)
+            if left > 0:
+                ids.append(rid)
+                sweeps.append(min(epoch_sweeps, left))
+        if ids:
+            executor.step([active[r][0] for r in ids], sweeps)
+            epochs += 1
+        if in_flight:
+            retire(*in_flight)
+        in_flight = (ids, sweeps) if ids else None
+        if not in_flight and not active and future and not waiting:
+            sleep(max(0.0, requests[future[0]].arrival - now()))
+    makespan = now()
+    res = [results[k] for k in sorted(results)]
+    return res, {"epochs": epochs, "makespan_s": makespan}
+
+
+def summarize(results, makespan_s):
+    ok = [r for r in results if not r.error]
+    lat = sorted(r.latency for r in ok)
+
+    def pct(p):
+        if not lat:
+            return float("nan")
+        k = min(len(lat) - 1, max(0, int(math.ceil(p / 100.0 * len(lat))) - 1))
+        return lat[k]
+
+    attempts = sum(r.L * r.L * r.sweeps for r in ok)
+    return {"requests": len(results), "completed": len(ok), "p50_s": pct(50), "p99_s": pct(99),
+            "mean_s": sum(lat) / len(lat) if lat else float("nan"),
+            "attempts": attempts, "makespan_s": makespan_s,
+            "attempts_per_ns": attempts / makespan_s / 1e9 if makespan_s > 0 else float("nan")}

@@ -90,10 +90,13 @@ def test_plan_switches_mid_run(b, o):
     G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref, "plan switches")
 
 
-def test_batch_equals_solo_and_oracle(b, o):
+@pytest.mark.parametrize("plan", ["RESIDENT", "STEPPED"])
+def test_batch_equals_solo_and_oracle(b, o, plan):
     """Uneven lattices (sizes, temperatures, fields, seeds, sweep counts,
-    including zero) in one persistent launch: each result is bit-identical
-    to the oracle's run of that lattice alone; a second batch continues."""
+    including zero) in one batch call, with either batch plan: each result is
+    bit-identical to the oracle's run of that lattice alone; a second batch
+    call continues from where the first stopped."""
+    bplan = getattr(b, "ISING_BATCH_" + plan)
     rng = np.random.default_rng(5)
     runs = []
     for k in range(40):
@@ -103,11 +106,11 @@ def test_batch_equals_solo_and_oracle(b, o):
                           sweeps=int(rng.integers(0, 25))))
     runs.append(W.Run(L=64, T=0.2, seed=3, sweeps=10))  # thresholds of 0: exact compare
     ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, b.ISING_PLAN_TWO_PASS) for r in runs]
-    G.log("batch of 41, first call")
-    b.ising_sweep_batch(ctxs, [r.sweeps for r in runs])
-    extra = [int(rng.integers(0, 6)) for _ in runs]
-    G.log("batch of 41, second call")
-    b.ising_sweep_batch(ctxs, extra)
+    G.log(f"batch of 41 ({plan}), first call")
+    b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], bplan)
+    extra = [int(rng.integers(0, 40)) for _ in runs]
+    G.log(f"batch of 41 ({plan}), second call")
+    b.ising_sweep_batch_plan(ctxs, extra, bplan)
     for r, ctx, e in zip(runs, ctxs, extra):
         obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
         spins = b.ising_copy_spins(ctx, r.L)
