@@ -46,6 +46,12 @@ def load(path=None):
     lib.oracle_window_run.restype = i32
     lib.oracle_init_window.argtypes = [u32, u64, dbl, u32, u32, u32, p]
     lib.oracle_init_window.restype = i32
+    lib.oracle_creutz_half_sweep.argtypes = [u32, u32, p, p]
+    lib.oracle_creutz_half_sweep.restype = i32
+    lib.oracle_demon_sum.argtypes = [u32, p]
+    lib.oracle_demon_sum.restype = C.c_int64
+    lib.oracle_creutz_run.argtypes = [u32, u64, i32, p, p, p, p, p]
+    lib.oracle_creutz_run.restype = i32
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_set_threads.restype = i32
     lib.oracle_get_threads.argtypes = []
@@ -127,6 +133,25 @@ class Oracle:
         if rc != 0:
             raise ValueError(f"oracle_run failed ({rc})")
         return B, M
+
+    def creutz_run(self, s, d, n, reverse=False, series=True):
+        """Creutz demon sweeps in place (spins s, demons d: uint8 (L, L));
+        returns (B, M, D) series of length n (or Nones)."""
+        L = s.shape[0]
+        assert d.dtype == np.uint8 and d.shape == s.shape and d.flags.c_contiguous
+        if series:
+            B, M, D = (np.zeros(n, dtype=np.int64) for _ in range(3))
+            args = (_ptr(B), _ptr(M), _ptr(D))
+        else:
+            B = M = D = None
+            args = (None, None, None)
+        rc = self.lib.oracle_creutz_run(L, n, 1 if reverse else 0, _ptr(s), _ptr(d), *args)
+        if rc != 0:
+            raise ValueError("invalid Creutz arguments")
+        return B, M, D
+
+    def demon_sum(self, d):
+        return int(self.lib.oracle_demon_sum(d.shape[0], _ptr(d)))
 
     def fnv1a64(self, s):
         b = np.ascontiguousarray(s).view(np.uint8)

@@ -62,45 +62,56 @@ __device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem&
     }
 }
 
+// Per-wave (sad, ups) partials of the last kFlush sweeps live in LDS and are
+// summed into the series every kFlush sweeps, so no sweep waits on a global
+// store before its barrier.
+constexpr uint32_t kFlush = 64;
+constexpr uint32_t kMaxWaves = kBatchThreads / 64;
+
 template <int CW, bool EXACT, typename PT>
 __device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem& it, PT p0, PT p1,
-                                            int64_t (*red)[16]) {
+                                            uint32_t (*part)[kMaxWaves][2]) {
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t nwaves = blockDim.x >> 6;
+    const uint32_t total = it.L * (it.Hw / CW);  // colour-1 chunks of the lattice
+    const int64_t words = (int64_t)total * CW;   // colour-1 words of the lattice
+    auto flush = [&](uint32_t first, uint32_t count) {
+        // thread k < count sums sweep first + k over the waves
+        if (threadIdx.x < count) {
+            const uint32_t slot = (first + threadIdx.x) % kFlush;
+            int64_t ss = 0, su = 0;
+            for (uint32_t w = 0; w < nwaves; ++w) {
+                ss += part[slot][w][0];
+                su += part[slot][w][1];
+            }
+            it.series[2 * (first + threadIdx.x)] = 16 * words - 2 * ss;
+            it.series[2 * (first + threadIdx.x) + 1] = 2 * su - 8 * words;
+        }
+    };
     for (uint32_t s = 0; s < it.n; ++s) {
         const uint32_t t = it.t0 + s;
         uint32_t sad = 0, ups = 0;
         colour_pass<CW, false, EXACT>(lt, it, p0, p1, 0u, t, sad, ups);
         __syncthreads();
         colour_pass<CW, true, EXACT>(lt, it, p0, p1, 1u, t, sad, ups);
-        // words of colour 1 this thread updated
-        const uint32_t total = it.L * (it.Hw / CW);
-        const uint32_t mine = threadIdx.x < total ? (total - 1 - threadIdx.x) / blockDim.x + 1 : 0u;
-        const int64_t nw = (int64_t)mine * CW;
-        int64_t b = 16 * nw - 2 * (int64_t)sad;
-        int64_t m = 2 * (int64_t)ups - 8 * nw;
+        // 32-bit wave sums (a thread covers at most a few hundred words per
+        // pass here, far from overflow); sweep totals are formed in 64 bits
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
-            b += __shfl_xor(b, off, 64);
-            m += __shfl_xor(m, off, 64);
+            sad += __shfl_xor(sad, off, 64);
+            ups += __shfl_xor(ups, off, 64);
         }
         if (lane == 0) {
-            red[0][wv] = b;
-            red[1][wv] = m;
+            part[s % kFlush][wv][0] = sad;
+            part[s % kFlush][wv][1] = ups;
         }
+        // separates colour 1 of sweep s from colour 0 of sweep s+1, and makes
+        // the partials visible to the flush
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int64_t sb = 0, sm = 0;
-            for (uint32_t w = 0; w < nwaves; ++w) {
-                sb += red[0][w];
-                sm += red[1][w];
-            }
-            it.series[2 * s] = sb;
-            it.series[2 * s + 1] = sm;
-        }
-        // the next colour-0 pass reads this sweep's colour 1, and red[] is
-        // not written again before two more barriers
+        if ((s + 1) % kFlush == 0) flush(s + 1 - kFlush, kFlush);
     }
+    const uint32_t rem = it.n % kFlush;
+    if (rem) flush(it.n - rem, rem);
 }
 
 }  // namespace
@@ -109,7 +120,7 @@ __device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem&
 // this workgroup's LDS copy).
 template <bool EXACT, typename PT>
 __device__ __forceinline__ void run_any(const LdsTable& lt, const BatchItem& it, PT p0, PT p1,
-                                        int64_t (*red)[16]) {
+                                        uint32_t (*red)[kMaxWaves][2]) {
     if (it.cw == 4) run_lattice<4, EXACT>(lt, it, p0, p1, red);
     else if (it.cw == 2) run_lattice<2, EXACT>(lt, it, p0, p1, red);
     else run_lattice<1, EXACT>(lt, it, p0, p1, red);
@@ -119,7 +130,7 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __rest
                                                          const uint32_t* __restrict__ order, BatchHeader* hdr) {
     __shared__ LdsTable lt;
     __shared__ uint32_t s_slot;
-    __shared__ int64_t red[2][16];
+    __shared__ uint32_t red[kFlush][kMaxWaves][2];
     // lattices of at most kBatchLdsBytes run from this LDS copy
     __shared__ uint32_t lat[kBatchLdsBytes / 4];
     const uint32_t count = hdr->count;

@@ -205,6 +205,9 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         it.L = c->L;
         it.Hw = c->L / 8u;
         it.cw = (it.Hw % 4u == 0u) ? 4u : (it.Hw % 2u == 0u) ? 2u : 1u;
+        // a lattice too small to give every thread of the resident
+        // workgroup a chunk uses one word per thread (latency, not width)
+        if (!stepped && (uint64_t)it.L * it.Hw <= 2ull * batch_block_threads()) it.cw = 1u;
         it.t0 = (uint32_t)c->t;
         it.n = (uint32_t)n[k];
         it.k0 = (uint32_t)c->p.seed;

@@ -74,7 +74,10 @@ constexpr uint32_t kResidentMaxL = 128;
 // Batches whose largest side is at most this use the resident kernel.
 constexpr uint32_t kResidentBatchMaxL = 256;
 // Fused tiles wanted per launch (one wave each) before a taller/wider tile is used.
-constexpr uint32_t kFusedMinTiles = 4096;
+constexpr uint32_t kFusedMinTiles = 16384;
+// The autotuner replaces the default plan only when a candidate is faster
+// by more than this fraction (timing noise must not flip the choice).
+constexpr float kTuneMargin = 0.03f;
 
 static uint32_t default_cw(uint32_t L) {
     const uint32_t Hw = L / 8u;
@@ -619,6 +622,18 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
     float best_ms = 0.f;
     Plan best = ctx->plan;
     bool have = false;
+    // the default plan for this side is timed first and kept unless beaten
+    Plan dflt;
+    if (plan_for(L, L % 8u ? ISING_PLAN_GENERIC : (L <= kResidentMaxL ? ISING_PLAN_RESIDENT : ISING_PLAN_FUSED),
+                 0, 0, &dflt) ||
+        plan_for(L, ISING_PLAN_TWO_PASS, 0, 0, &dflt)) {
+        for (size_t k = 0; k < cands.size(); ++k) {
+            if (cands[k].kind == dflt.kind && cands[k].cw == dflt.cw && cands[k].rows == dflt.rows) {
+                std::swap(cands[0], cands[k]);
+                break;
+            }
+        }
+    }
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = ISING_EDEVICE;
     for (size_t k = 0; rc == ISING_OK && k < cands.size(); ++k) {
         tmp->plan = cands[k];
@@ -642,7 +657,7 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
         if (rc == ISING_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = ISING_EDEVICE;
         if (rc != ISING_OK) break;
         tmp->series_len = 0;
-        if (!have || ms < best_ms) {
+        if (!have || ms < best_ms * (1.0f - kTuneMargin)) {
             best_ms = ms;
             best = cands[k];
             have = true;

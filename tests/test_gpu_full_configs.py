@@ -1,0 +1,82 @@
+"""Full-size batched and served configurations, in the launch configuration
+bench.py times, checked on outputs the oracle can compute one by one and on
+properties that hold at any size."""
+import numpy as np
+import pytest
+
+from paper_cs_0312006_amd import serve
+from paper_cs_0312006_amd import workloads as W
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_cs_0312006_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def o():
+    from oracle import ref
+    orc = ref.Oracle()
+    orc.set_threads(G.host_threads())
+    return orc
+
+
+@pytest.mark.parametrize("plan", ["STEPPED", "RESIDENT"])
+def test_batched_1024_lattices_10000_sweeps(b, o, plan):
+    """1024 lattices, L = 32 + 16 U{0..62}, T ~ U[1.5, 3.5], seed = index,
+    10000 sweeps each, one batch call: the four smallest lattices equal the
+    oracle over all 10000 sweeps; every lattice's series satisfies the
+    integer invariants and ends at the observables of its final lattice."""
+    runs = W.batched(count=1024, sweeps=10000)
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    G.log(f"batched 1024 x 10000 sweeps ({plan})")
+    b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], getattr(b, "ISING_BATCH_" + plan))
+    small = sorted(range(len(runs)), key=lambda k: runs[k].L)[:4]
+    try:
+        for k, (r, c) in enumerate(zip(runs, ctxs)):
+            obs, B, M = b.ising_observables(c, b.ISING_OBS_SERIES | (b.ISING_OBS_HASH if k in small else 0))
+            assert len(B) == 10000 and obs.sweeps_done == 10000
+            N = r.L * r.L
+            assert np.all(B % 4 == 0) and np.all(M % 2 == 0)
+            assert np.all(np.abs(B) <= 2 * N) and np.all(np.abs(M) <= N)
+            assert (int(B[-1]), int(M[-1])) == (obs.bond_sum, obs.mag_sum)
+            if k in small:
+                G.log(f"batched lattice {k} L={r.L} vs oracle")
+                ref = G.oracle_run(o, r)
+                spins = b.ising_copy_spins(c, r.L)
+                G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref, f"lattice {k}")
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
+
+
+def test_served_full_size_requests_equal_solo(b, o):
+    """Twelve requests drawn from the served configuration (L up to 2048,
+    up to 20000 sweeps) through the continuous-batching server at 1000
+    requests/s: each result is bit-identical to the same request run alone;
+    those with L = 64 also equal the oracle."""
+    reqs = W.request_stream(1000.0, count=256)
+    pick = sorted(range(256), key=lambda k: reqs[k].run.L)
+    chosen = pick[:3] + pick[-3:] + pick[120:126]
+    t0 = min(reqs[k].arrival for k in chosen)
+    sub = [W.Request(reqs[k].arrival - t0, reqs[k].run) for k in chosen]
+    G.log("served 12 full-size requests")
+    res, stats = serve.serve(sub, serve.GpuExecutor(), epoch_sweeps=64)
+    assert all(not r.error for r in res)
+    for r in res:
+        run = sub[r.rid].run
+        ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+        b.ising_sweep(ctx, run.sweeps)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        b.ising_destroy(ctx)
+        assert (r.lattice_hash, r.bond_sum, r.mag_sum) == (obs.lattice_hash, obs.bond_sum, obs.mag_sum)
+        if run.L == 64:
+            G.log(f"served request L=64 sweeps={run.sweeps} vs oracle")
+            s = o.init(run.L, run.seed, run.p_up)
+            Bo, Mo = o.run(s, run.J, run.h, run.T, run.seed, 0, run.sweeps, series=False)
+            assert r.lattice_hash == o.fnv1a64(s)
