@@ -205,6 +205,38 @@ int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
  * Synchronises. The chosen plan is readable with ising_plan_info. */
 int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps);
 
+/* ---- Creutz demon dynamics (Section 2.2) --------------------------------
+ * The deterministic checkerboard dynamics the paper cites as the faster,
+ * random-number-free alternative to Metropolis sweeps. Every site carries a
+ * demon energy d in units of 4J, 0 <= d <= 255 (zero field, J > 0 only).
+ * A pass over colour c flips a site iff its demon can pay for the move:
+ * e = dE / 4J = s * (sum of the four neighbour spins) / 2, flip iff e <= d
+ * and d - e <= 255, then d -= e. A sweep is the colour-0 pass followed by
+ * the colour-1 pass; -B + 4 * (demon total) is conserved exactly and the
+ * reversed sweep (colour 1 then colour 0) undoes a sweep exactly. The demon
+ * total, read as a thermometer, gives the temperature: in equilibrium each
+ * demon is Boltzmann-distributed, <d> = 1 / (exp(4J / T) - 1). */
+
+/* Give the context demons: host canonical bytes (row-major L*L, n >= L*L)
+ * or, with host == NULL, every demon = fill. Allocates the demon buffer on
+ * first use (L*L bytes). Synchronises. Errors: EINVAL (NULL ctx, n too
+ * small), EUNSUPPORTED (h != 0 or J <= 0), ENOMEM, ESTATE, EDEVICE. */
+int ising_creutz_init(ising_ctx* ctx, const uint8_t* host, size_t n, uint8_t fill);
+
+/* Enqueue n Creutz sweeps (reverse != 0: n reversed sweeps) on the
+ * context's stream and record (B, M) after each in the per-sweep series,
+ * as ising_sweep does. Draws no random numbers and leaves the Metropolis
+ * sweep index t unchanged. Asynchronous. Errors: EINVAL (NULL ctx), ESTATE
+ * (no demons: call ising_creutz_init first; or poisoned), ENOMEM, EDEVICE. */
+int ising_creutz_sweep(ising_ctx* ctx, uint64_t n, int reverse);
+
+/* Demon total (units of 4J) into *out. Synchronises. Errors as above. */
+int ising_demon_sum(ising_ctx* ctx, int64_t* out);
+
+/* Copy the demons to host memory `host` of n >= L*L bytes, canonical
+ * row-major layout. Synchronises. */
+int ising_copy_demons(ising_ctx* ctx, uint8_t* host, size_t n);
+
 /* Release the context and its library-owned device memory. NULL is a no-op.
  * Synchronises the context's stream first. */
 int ising_destroy(ising_ctx* ctx);

@@ -80,6 +80,10 @@ SIGNATURES = {
                                   C.POINTER(C.c_uint32)]),
     "ising_plan_set": (C.c_int, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
     "ising_tune": (C.c_int, [C.c_void_p, C.c_uint32]),
+    "ising_creutz_init": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint8]),
+    "ising_creutz_sweep": (C.c_int, [C.c_void_p, C.c_uint64, C.c_int]),
+    "ising_demon_sum": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "ising_copy_demons": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ising_destroy": (C.c_int, [C.c_void_p]),
     "ising_strerror": (C.c_char_p, [C.c_int]),
 }
@@ -219,6 +223,33 @@ def ising_plan_set(ctx, plan, cw=0, rows=0):
 
 def ising_tune(ctx, trial_sweeps=4):
     _check(lib().ising_tune(ctx, int(trial_sweeps)), "ising_tune")
+
+
+def ising_creutz_init(ctx, demons=None, fill=0):
+    """Demons from an (L, L) uint8 array (canonical layout) or, when None,
+    every demon = fill."""
+    if demons is None:
+        rc = lib().ising_creutz_init(ctx, None, 0, int(fill))
+    else:
+        a = np.ascontiguousarray(demons, dtype=np.uint8)
+        rc = lib().ising_creutz_init(ctx, a.ctypes.data, a.size, 0)
+    _check(rc, "ising_creutz_init")
+
+
+def ising_creutz_sweep(ctx, n, reverse=False):
+    _check(lib().ising_creutz_sweep(ctx, int(n), 1 if reverse else 0), "ising_creutz_sweep")
+
+
+def ising_demon_sum(ctx):
+    v = C.c_int64()
+    _check(lib().ising_demon_sum(ctx, C.byref(v)), "ising_demon_sum")
+    return v.value
+
+
+def ising_copy_demons(ctx, L):
+    out = np.empty((L, L), dtype=np.uint8)
+    _check(lib().ising_copy_demons(ctx, out.ctypes.data, out.size), "ising_copy_demons")
+    return out
 
 
 def ising_destroy(ctx):

@@ -28,6 +28,26 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// Consecutive logical blocks land on the same XCD (blocks are dealt
+// round-robin over the 8 XCDs), so neighbouring rows share an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t nblocks) {
+    const uint32_t b = blockIdx.x;
+    if ((nblocks & 7u) != 0u) return b;
+    return (b & 7u) * (nblocks >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // a ^ b ^ c in one gfx950 VALU op (truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);

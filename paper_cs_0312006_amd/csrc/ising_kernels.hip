@@ -17,26 +17,6 @@ namespace ising {
 // Small helpers
 // ---------------------------------------------------------------------------
 
-// Consecutive logical blocks land on the same XCD (blocks are dealt
-// round-robin over the 8 XCDs), so neighbouring rows share an L2.
-__device__ __forceinline__ uint32_t xcd_block(uint32_t nblocks) {
-    const uint32_t b = blockIdx.x;
-    if ((nblocks & 7u) != 0u) return b;
-    return (b & 7u) * (nblocks >> 3) + (b >> 3);
-}
-
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Block-wide sum of two int64 values, added atomically to out[0], out[1].
 __device__ __forceinline__ void block_add2(int64_t a, int64_t b, int64_t* out) {
     __shared__ int64_t part[2][16];

@@ -125,6 +125,18 @@ uint32_t multi_vblocks(uint32_t L, uint32_t cw);
 hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_start, MultiHeader* hdr,
                                    uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
 
+// Creutz demon dynamics (ising_creutz.hip): dm holds the demon planes, in
+// the spin planes' layout. A sweep is two in-place passes; the word path
+// (L % 8 == 0) writes the finished sweep's (B, M) partials into part
+// (creutz_blocks() pairs) and reduces `red` first.
+uint32_t creutz_blocks(const Planes& pl);
+hipError_t launch_creutz_sweep(const Planes& pl, const Planes& dm, bool reverse, int64_t* part,
+                               const PartialReduce& red, hipStream_t s);
+hipError_t launch_creutz_sweep_sites(const Planes& pl, const Planes& dm, bool reverse, hipStream_t s);
+hipError_t launch_demon_sum(const uint8_t* d, uint64_t n, int64_t* out, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_bytes_to_canonical(const Planes& pl, uint8_t* out, hipStream_t s);
+hipError_t launch_bytes_from_canonical(const Planes& pl, const uint8_t* in, hipStream_t s);
 hipError_t launch_to_canonical(const Planes& pl, int8_t* out, hipStream_t s);
 hipError_t launch_from_canonical(const Planes& pl, const int8_t* in, hipStream_t s);
 

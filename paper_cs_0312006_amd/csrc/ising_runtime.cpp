@@ -679,6 +679,94 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
     return ISING_OK;
 }
 
+int ising_creutz_init(ising_ctx* ctx, const uint8_t* host, size_t n, uint8_t fill) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (host && n < N) return ISING_EINVAL;
+    if (ctx->p.h != 0.0 || !(ctx->p.J > 0.0)) return ISING_EUNSUPPORTED;
+    if (!ctx->demon) {
+        if (hipMalloc(&ctx->demon, N) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->demon = nullptr;
+            return ISING_ENOMEM;
+        }
+    }
+    if (!ctx->cpart && ctx->L % 8u == 0u) {
+        if (hipMalloc(&ctx->cpart, (size_t)creutz_blocks(ctx_planes(ctx)) * 2 * sizeof(int64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->cpart = nullptr;
+            return ISING_ENOMEM;
+        }
+    }
+    const Planes dm = planes_of(ctx->demon, ctx->L);
+    if (host) {
+        rc = ensure_canonical(ctx);
+        if (rc != ISING_OK) return rc;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->canon, host, N, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, launch_bytes_from_canonical(dm, reinterpret_cast<const uint8_t*>(ctx->canon), ctx->stream));
+    } else {
+        HIP_TRY(ctx, launch_fill_u8(ctx->demon, N, fill, ctx->stream));
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISING_OK;
+}
+
+int ising_creutz_sweep(ising_ctx* ctx, uint64_t n, int reverse) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (!ctx->demon) return ISING_ESTATE;
+    if (n == 0) return ISING_OK;
+    rc = ctx_reserve_series(ctx, n);
+    if (rc != ISING_OK) return rc;
+    int64_t* ser = ctx->series + 2 * ctx->series_len;
+    const Planes pl = ctx_planes(ctx), dm = planes_of(ctx->demon, ctx->L);
+    if (ctx->L % 8u == 0u) {
+        const uint32_t nb = creutz_blocks(pl);
+        for (uint64_t k = 0; k < n; ++k) {
+            PartialReduce red{nullptr, 0, nullptr};
+            if (k > 0) red = PartialReduce{ctx->cpart, nb, ser + 2 * (k - 1)};
+            HIP_TRY(ctx, launch_creutz_sweep(pl, dm, reverse != 0, ctx->cpart, red, ctx->stream));
+        }
+        HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->cpart, nb, ser + 2 * (n - 1)}, ctx->stream));
+    } else {
+        for (uint64_t k = 0; k < n; ++k) {
+            HIP_TRY(ctx, launch_creutz_sweep_sites(pl, dm, reverse != 0, ctx->stream));
+            HIP_TRY(ctx, launch_observe(pl, ser + 2 * k, ctx->stream));
+        }
+    }
+    ctx->series_len += n;
+    return ISING_OK;
+}
+
+int ising_demon_sum(ising_ctx* ctx, int64_t* out) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (!out) return ISING_EINVAL;
+    if (!ctx->demon) return ISING_ESTATE;
+    HIP_TRY(ctx, launch_demon_sum(ctx->demon, (uint64_t)ctx->L * ctx->L, ctx->scratch + 2, ctx->stream));
+    int64_t v = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&v, ctx->scratch + 2, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    *out = v;
+    return ISING_OK;
+}
+
+int ising_copy_demons(ising_ctx* ctx, uint8_t* host, size_t n) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (!host || n < N) return ISING_EINVAL;
+    if (!ctx->demon) return ISING_ESTATE;
+    rc = ensure_canonical(ctx);
+    if (rc != ISING_OK) return rc;
+    HIP_TRY(ctx, launch_bytes_to_canonical(planes_of(ctx->demon, ctx->L), reinterpret_cast<uint8_t*>(ctx->canon),
+                                           ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(host, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return ISING_OK;
+}
+
 int ising_destroy(ising_ctx* ctx) {
     if (!ctx) return ISING_OK;
     (void)hipSetDevice(ctx->device);
@@ -688,6 +776,8 @@ int ising_destroy(ising_ctx* ctx) {
         if (ctx->part[k]) (void)hipFree(ctx->part[k]);
     }
     if (ctx->series) (void)hipFree(ctx->series);
+    if (ctx->demon) (void)hipFree(ctx->demon);
+    if (ctx->cpart) (void)hipFree(ctx->cpart);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->canon) (void)hipFree(ctx->canon);
     if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);

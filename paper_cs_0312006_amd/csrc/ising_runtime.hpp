@@ -45,6 +45,8 @@ struct ising_ctx {
     uint32_t part_cap = 0;       // pairs per partial buffer
     int64_t* scratch = nullptr;  // 4 int64 for observables
     int8_t* canon = nullptr;     // N bytes, canonical layout staging
+    uint8_t* demon = nullptr;    // Creutz demons (N bytes, colour-plane layout), once initialised
+    int64_t* cpart = nullptr;    // Creutz per-block (B, M) partials
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;
     hipError_t last_hip = hipSuccess;

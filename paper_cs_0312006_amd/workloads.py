@@ -75,3 +75,16 @@ def random_lattice(L, seed, p_up=0.5):
     """A canonical +1/-1 int8 lattice with i.i.d. spins (NumPy generator)."""
     rng = np.random.default_rng(seed)
     return np.where(rng.random((L, L)) < p_up, 1, -1).astype(np.int8)
+
+
+def random_demons(L, seed, hi):
+    """Canonical (L, L) uint8 demon energies, i.i.d. uniform on 0..hi
+    (NumPy generator); units of 4J."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, hi + 1, size=(L, L), dtype=np.uint8)
+
+
+# Creutz demon dynamics at the headline lattice size: hot start (p = 0.5)
+# with empty demons, so the total energy is near 0 and the demons settle at
+# a temperature of about 2.56 J.
+CREUTZ = Run(L=32768, seed=11, p_up=0.5, sweeps=500)

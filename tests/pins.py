@@ -7,6 +7,7 @@ at least one of them.
 """
 import numpy as np
 
+from paper_cs_0312006_amd import workloads
 from tests import physics
 
 
@@ -148,3 +149,69 @@ def check_observables_definition(o, sizes=(2, 4, 8, 12), seed=4):
                 b_edges += int(s[i, j]) * int(s[i, (j + 1) % L]) + int(s[i, j]) * int(s[(i + 1) % L, j])
         up = int((s > 0).sum())
         assert o.observables(s) == (b_edges, up - (L * L - up)), L
+
+
+# ---------------------------------------------------------------------------
+# Creutz demon dynamics (the deterministic alternative of Section 2.2)
+# ---------------------------------------------------------------------------
+def creutz_start(o, L, seed, p_up, demons):
+    """Seeded start: spins from the oracle's initial draw, demons either a
+    constant or uniform on 0..demons[1] (demons = ("uniform", hi))."""
+    s = o.init(L, seed, p_up)
+    if isinstance(demons, tuple):
+        d = workloads.random_demons(L, seed, demons[1])
+    else:
+        d = np.full((L, L), demons, dtype=np.uint8)
+    return s, d
+
+
+def check_creutz_conservation(o, L, seed, p_up, demons, sweeps=200):
+    """Spin energy plus demon energy, -B + 4 D in units of J, is the same
+    after every sweep, and the series agree with recomputed observables."""
+    s, d = creutz_start(o, L, seed, p_up, demons)
+    b0, _ = o.observables(s)
+    e0 = -b0 + 4 * o.demon_sum(d)
+    B, M, D = o.creutz_run(s, d, sweeps)
+    assert np.all(-B + 4 * D == e0), "energy not conserved"
+    assert (int(B[-1]), int(M[-1])) == o.observables(s)
+    assert int(D[-1]) == int(d.astype(np.int64).sum())
+
+
+def check_creutz_reversible(o, L, seed, p_up, demons, sweeps=100):
+    """n sweeps followed by n reversed sweeps restore spins and demons."""
+    s, d = creutz_start(o, L, seed, p_up, demons)
+    s0, d0 = s.copy(), d.copy()
+    o.creutz_run(s, d, sweeps, series=False)
+    moved = not np.array_equal(s, s0)
+    o.creutz_run(s, d, sweeps, reverse=True, series=False)
+    assert moved, "dynamics froze: the reversibility check would be vacuous"
+    assert np.array_equal(s, s0) and np.array_equal(d, d0), "reversed sweeps do not undo the forward ones"
+
+
+def demon_temperature(d_mean):
+    """Temperature (units of J) at which a demon with energies 4J k,
+    k = 0, 1, 2, ..., has mean k = d_mean: <k> = 1 / (exp(4 / T) - 1)."""
+    return 4.0 / np.log1p(1.0 / d_mean)
+
+
+def check_creutz_thermometer(o, L, seed, p_up, sweeps=12_000, burn=2_000, n_bins=40, nsig=4.0):
+    """Creutz's microcanonical chain, read through its demons, reproduces
+    the canonical energy: the mean energy per site equals the exact finite-
+    lattice energy (Kaufman) at the temperature the mean demon energy
+    indicates. Residuals are taken per time bin, so the correlated errors
+    of the energy and of the demon temperature are both accounted for."""
+    s, d = creutz_start(o, L, seed, p_up, 0)
+    B, M, D = o.creutz_run(s, d, sweeps)
+    N = L * L
+    u = -B[burn:] / N
+    dm = D[burn:] / N
+    k = len(u) // n_bins
+    r = []
+    for b in range(n_bins):
+        ub = u[b * k:(b + 1) * k].mean()
+        T = demon_temperature(dm[b * k:(b + 1) * k].mean())
+        r.append(ub - physics.kaufman_energy(L, T))
+    r = np.array(r)
+    se = r.std(ddof=1) / np.sqrt(n_bins)
+    assert abs(r.mean()) < nsig * se + 2e-4, (r.mean(), se)
+    return demon_temperature(dm.mean())

@@ -16,13 +16,15 @@ SRC = open(obuild.SRC).read()
 
 MUTANTS = {
     # every site updated in each pass (no checkerboard): not the Ising chain
-    "no_checkerboard": ("if (((i + j) & 1u) != c) continue;", "(void)0;"),
+    # (the same test guards the Creutz pass further down: mutate the first)
+    "no_checkerboard": ("if (((i + j) & 1u) != c) continue;", "(void)0;", 0),
     # wrong sign of the energy change
     "energy_sign": ("double dE = 2.0 * s * (J * n + h);", "double dE = -2.0 * s * (J * n + h);"),
     # field term dropped
     "field_dropped": ("double dE = 2.0 * s * (J * n + h);", "double dE = 2.0 * s * (J * n);"),
     # left neighbour counted twice, right one never
-    "wrong_neighbour": ("s[(size_t)i * L + rt];", "s[(size_t)i * L + lf];"),
+    "wrong_neighbour": ("s[(size_t)i * L + rt];\n            int8_t me",
+                        "s[(size_t)i * L + lf];\n            int8_t me"),
     # bond sum counts the right neighbour twice and misses the lower one
     "bond_sum": ("b += (int64_t)(me * (right + down));", "b += (int64_t)(me * (right + right));"),
     # Philox key words swapped in the round
@@ -30,6 +32,15 @@ MUTANTS = {
     # colour order reversed (a valid chain, but not the frozen one)
     "colour_order": ("oracle_half_sweep(L, thr, seed, t, 0, s);\n        oracle_half_sweep(L, thr, seed, t, 1, s);",
                      "oracle_half_sweep(L, thr, seed, t, 1, s);\n        oracle_half_sweep(L, thr, seed, t, 0, s);"),
+    # Creutz: demon credited with the wrong sign of the energy change
+    "creutz_sign": ("int e = s[at] * n / 2;", "int e = -s[at] * n / 2;"),
+    # Creutz: demon capacity not enforced (the byte wraps)
+    "creutz_cap": ("if (e <= dem && dem - e <= 255) {", "if (e <= dem) {"),
+    # Creutz: a demon must hold strictly more than the move costs
+    "creutz_strict": ("if (e <= dem && dem - e <= 255) {", "if (e < dem && dem - e <= 255) {"),
+    # Creutz: left neighbour counted twice
+    "creutz_neighbour": ("s[(size_t)i * L + rt];\n            size_t at",
+                         "s[(size_t)i * L + lf];\n            size_t at"),
     # initial state uses the wrong comparison
     "init_compare": ("s[(size_t)i * L + j] = ((uint64_t)u < pthr)", "s[(size_t)i * L + j] = ((uint64_t)u >= pthr)"),
 }
@@ -39,10 +50,20 @@ MUTANTS = {
 def mutants(tmp_path_factory):
     out = {}
     d = tmp_path_factory.mktemp("mutants")
-    for name, (old, new) in MUTANTS.items():
-        assert SRC.count(old) == 1, name
+    for name, spec in MUTANTS.items():
+        old, new = spec[:2]
+        if len(spec) == 3:  # mutate the k-th of several occurrences
+            k = spec[2]
+            assert SRC.count(old) > k, name
+            at = -1
+            for _ in range(k + 1):
+                at = SRC.index(old, at + 1)
+            text = SRC[:at] + new + SRC[at + len(old):]
+        else:
+            assert SRC.count(old) == 1, name
+            text = SRC.replace(old, new)
         src = d / f"{name}.c"
-        src.write_text(SRC.replace(old, new))
+        src.write_text(text)
         lib = str(d / f"lib{name}.so")
         obuild.compile_oracle(str(src), lib)
         out[name] = Oracle(lib)
@@ -100,3 +121,22 @@ def test_real_oracle_passes_the_same_checks(oracle1):
     pins.check_bm_histogram(oracle1, 4, 1.0, 0.0, 2.269185, sweeps=100_000)
     pins.check_bruteforce(oracle1, 4, 1.0, 0.0, 2.269185, sweeps=50_000)
     pins.check_bruteforce(oracle1, 4, 1.0, 0.1, 2.269185, sweeps=50_000)
+
+
+@pytest.mark.parametrize("name", ["creutz_sign", "creutz_neighbour", "creutz_cap"])
+def test_creutz_conservation_catches(mutants, name):
+    o = mutants[name]
+    caught = any(_fails(pins.check_creutz_conservation, o, L, 5, 0.5, dem)
+                 for L, dem in [(16, ("uniform", 3)), (32, 255)])
+    assert caught
+
+
+def test_creutz_reversibility_catches_strict_demon(mutants):
+    o = mutants["creutz_strict"]
+    assert _fails(pins.check_creutz_reversible, o, 16, 4, 0.5, 0)
+
+
+def test_real_oracle_passes_the_creutz_checks(oracle1):
+    for L, dem in [(16, ("uniform", 3)), (32, 255)]:
+        pins.check_creutz_conservation(oracle1, L, 5, 0.5, dem)
+    pins.check_creutz_reversible(oracle1, 16, 4, 0.5, 0)
