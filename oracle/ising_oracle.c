@@ -374,3 +374,113 @@ int oracle_creutz_run(uint32_t L, uint64_t n, int reverse, int8_t *s, uint8_t *d
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Site percolation in a porous medium (Section 2.3).
+ *
+ * Medium: an L x L lattice with open (non-periodic) boundaries. Each site
+ * draws R and is a pore iff R <= P (the porosity). As for the Ising draws,
+ * R = (u + 1) / 2^32 with u a 32-bit Philox4x32-10 output, so the site is a
+ * pore iff u < floor(P * 2^32). Reading used here for the keying: site
+ * ord = i*L + j takes word ord % 4 of counter (ord / 4, 0, 0, 2) under key
+ * (seed low, seed high); domain 2 keeps these draws apart from the Ising
+ * ones (domains 0 and 1).
+ *
+ * Invasion: the cluster starts at the invasion point(s), pores only, and
+ * spreads in passes; pass k adds every pore that shares an edge with a
+ * site already in the cluster. Reading used here: the invasion source is
+ * either every pore of row 0 (the medium's top face, so the cluster spans
+ * when it reaches row L-1) or one point (i0, j0). The arrival pass of a
+ * site is its breadth-first distance from the sources through pores, -1 if
+ * it is never invaded; the steady state is reached after (max arrival)
+ * passes, and one more pass changes nothing.
+ * ---------------------------------------------------------------------- */
+#define ORACLE_PERC_TOP_ROW 0u
+#define ORACLE_PERC_POINT 1u
+
+int oracle_perc_medium(uint32_t L, double P, uint64_t seed, uint8_t *pore)
+{
+    if (L < 1 || L > ORACLE_MAX_L || !(P >= 0.0 && P <= 1.0) || !pore) return ORACLE_EINVAL;
+    uint64_t pthr = (uint64_t)floor(P * 4294967296.0);
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int rows = (int)L;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (int i = 0; i < rows; ++i) {
+        for (uint32_t j = 0; j < L; ++j) {
+            uint64_t ord = (uint64_t)i * L + j;
+            uint32_t ctr[4] = {(uint32_t)(ord >> 2), 0u, 0u, 2u};
+            uint32_t out[4];
+            oracle_philox4x32_10(ctr, key, out);
+            pore[ord] = ((uint64_t)out[ord & 3u] < pthr) ? 1u : 0u;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* Arrival passes by breadth-first search from the sources (a FIFO queue of
+ * site indices; each site enters it once). */
+int oracle_perc_invade(uint32_t L, const uint8_t *pore, uint32_t source, uint32_t i0, uint32_t j0,
+                       int32_t *arrival, uint32_t *queue)
+{
+    if (L < 1 || L > ORACLE_MAX_L || !pore || !arrival || !queue) return ORACLE_EINVAL;
+    if (source > ORACLE_PERC_POINT || (source == ORACLE_PERC_POINT && (i0 >= L || j0 >= L)))
+        return ORACLE_EINVAL;
+    size_t N = (size_t)L * L, head = 0, tail = 0;
+    for (size_t k = 0; k < N; ++k) arrival[k] = -1;
+    if (source == ORACLE_PERC_TOP_ROW) {
+        for (uint32_t j = 0; j < L; ++j)
+            if (pore[j]) {
+                arrival[j] = 0;
+                queue[tail++] = j;
+            }
+    } else {
+        size_t at = (size_t)i0 * L + j0;
+        if (pore[at]) {
+            arrival[at] = 0;
+            queue[tail++] = (uint32_t)at;
+        }
+    }
+    while (head < tail) {
+        size_t at = queue[head++];
+        uint32_t i = (uint32_t)(at / L), j = (uint32_t)(at % L);
+        size_t nb[4];
+        int cnt = 0;
+        if (i > 0) nb[cnt++] = at - L;
+        if (i + 1 < L) nb[cnt++] = at + L;
+        if (j > 0) nb[cnt++] = at - 1;
+        if (j + 1 < L) nb[cnt++] = at + 1;
+        for (int k = 0; k < cnt; ++k) {
+            if (pore[nb[k]] && arrival[nb[k]] < 0) {
+                arrival[nb[k]] = arrival[at] + 1;
+                queue[tail++] = (uint32_t)nb[k];
+            }
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* Summary of an arrival map: invaded sites, steady-state pass count (max
+ * arrival, 0 for an empty cluster), and spanning bits: 1 = the cluster
+ * holds a site of row 0 and one of row L-1, 2 = of column 0 and column L-1. */
+void oracle_perc_summary(uint32_t L, const int32_t *arrival, uint64_t *invaded, int32_t *max_arrival,
+                         uint32_t *spans)
+{
+    uint64_t n = 0;
+    int32_t mx = 0;
+    int top = 0, bottom = 0, left = 0, right = 0;
+    for (uint32_t i = 0; i < L; ++i) {
+        for (uint32_t j = 0; j < L; ++j) {
+            int32_t a = arrival[(size_t)i * L + j];
+            if (a < 0) continue;
+            ++n;
+            if (a > mx) mx = a;
+            top |= i == 0;
+            bottom |= i == L - 1;
+            left |= j == 0;
+            right |= j == L - 1;
+        }
+    }
+    *invaded = n;
+    *max_arrival = mx;
+    *spans = (uint32_t)((top && bottom) ? 1 : 0) | (uint32_t)((left && right) ? 2 : 0);
+}

@@ -52,6 +52,12 @@ def load(path=None):
     lib.oracle_demon_sum.restype = C.c_int64
     lib.oracle_creutz_run.argtypes = [u32, u64, i32, p, p, p, p, p]
     lib.oracle_creutz_run.restype = i32
+    lib.oracle_perc_medium.argtypes = [u32, dbl, u64, p]
+    lib.oracle_perc_medium.restype = i32
+    lib.oracle_perc_invade.argtypes = [u32, p, u32, u32, u32, p, p]
+    lib.oracle_perc_invade.restype = i32
+    lib.oracle_perc_summary.argtypes = [u32, p, p, p, p]
+    lib.oracle_perc_summary.restype = None
     lib.oracle_set_threads.argtypes = [i32]
     lib.oracle_set_threads.restype = i32
     lib.oracle_get_threads.argtypes = []
@@ -152,6 +158,34 @@ class Oracle:
 
     def demon_sum(self, d):
         return int(self.lib.oracle_demon_sum(d.shape[0], _ptr(d)))
+
+    # -- percolation (Section 2.3) -------------------------------------------
+    PERC_TOP_ROW = 0
+    PERC_POINT = 1
+
+    def perc_medium(self, L, P, seed):
+        """(L, L) uint8 pore map: 1 = pore."""
+        pore = np.zeros((L, L), dtype=np.uint8)
+        if self.lib.oracle_perc_medium(L, P, seed, _ptr(pore)) != 0:
+            raise ValueError("invalid medium arguments")
+        return pore
+
+    def perc_invade(self, pore, source=0, i0=0, j0=0):
+        """(L, L) int32 arrival passes (-1 = never invaded)."""
+        pore = np.ascontiguousarray(pore, dtype=np.uint8)
+        L = pore.shape[0]
+        arr = np.zeros((L, L), dtype=np.int32)
+        queue = np.zeros(L * L, dtype=np.uint32)
+        if self.lib.oracle_perc_invade(L, _ptr(pore), source, i0, j0, _ptr(arr), _ptr(queue)) != 0:
+            raise ValueError("invalid invasion arguments")
+        return arr
+
+    def perc_summary(self, arrival):
+        """(invaded sites, max arrival pass, spanning bits)."""
+        arrival = np.ascontiguousarray(arrival, dtype=np.int32)
+        n, mx, sp = C.c_uint64(), C.c_int32(), C.c_uint32()
+        self.lib.oracle_perc_summary(arrival.shape[0], _ptr(arrival), C.byref(n), C.byref(mx), C.byref(sp))
+        return n.value, mx.value, sp.value
 
     def fnv1a64(self, s):
         b = np.ascontiguousarray(s).view(np.uint8)

@@ -41,6 +41,17 @@ MUTANTS = {
     # Creutz: left neighbour counted twice
     "creutz_neighbour": ("s[(size_t)i * L + rt];\n            size_t at",
                          "s[(size_t)i * L + lf];\n            size_t at"),
+    # percolation: invasion wraps around top and bottom (periodic, not open)
+    "perc_wrap": ("if (i > 0) nb[cnt++] = at - L;", "nb[cnt++] = i > 0 ? at - L : at + (size_t)(L - 1) * L;"),
+    # percolation: arrival counts two passes per step
+    "perc_arrival": ("arrival[nb[k]] = arrival[at] + 1;", "arrival[nb[k]] = arrival[at] + 2;"),
+    # percolation: a diagonal neighbour also invades
+    "perc_diagonal": ("if (j + 1 < L) nb[cnt++] = at + 1;",
+                      "if (j + 1 < L) nb[cnt++] = at + 1;\n        size_t nb5 = (i + 1 < L && j + 1 < L) ? at + L + 1 : at;\n"
+                      "        if (pore[nb5] && arrival[nb5] < 0) { arrival[nb5] = arrival[at] + 1; queue[tail++] = (uint32_t)nb5; }"),
+    # percolation: porosity threshold taken as 1 - P
+    "perc_porosity": ("uint64_t pthr = (uint64_t)floor(P * 4294967296.0);\n    uint32_t key[2]",
+                      "uint64_t pthr = (uint64_t)floor((1.0 - P) * 4294967296.0);\n    uint32_t key[2]"),
     # initial state uses the wrong comparison
     "init_compare": ("s[(size_t)i * L + j] = ((uint64_t)u < pthr)", "s[(size_t)i * L + j] = ((uint64_t)u >= pthr)"),
 }
@@ -140,3 +151,24 @@ def test_real_oracle_passes_the_creutz_checks(oracle1):
     for L, dem in [(16, ("uniform", 3)), (32, 255)]:
         pins.check_creutz_conservation(oracle1, L, 5, 0.5, dem)
     pins.check_creutz_reversible(oracle1, 16, 4, 0.5, 0)
+
+
+@pytest.mark.parametrize("name", ["perc_wrap", "perc_arrival", "perc_diagonal"])
+def test_percolation_library_pins_catch(mutants, name):
+    from tests import test_oracle_percolation as tp
+    o = mutants[name]
+    caught = any(_fails(tp.test_cluster_and_arrival_match_library, o, L, P, seed)
+                 for L, P, seed in [(31, 0.59, 2), (64, 0.62, 3)])
+    assert caught
+
+
+def test_percolation_fraction_catches_porosity(mutants):
+    from tests import test_oracle_percolation as tp
+    assert _fails(tp.test_medium_fraction, mutants["perc_porosity"], 64, 0.3, 1)
+
+
+def test_real_oracle_passes_the_percolation_checks(oracle1):
+    from tests import test_oracle_percolation as tp
+    for L, P, seed in [(31, 0.59, 2), (64, 0.62, 3)]:
+        tp.test_cluster_and_arrival_match_library(oracle1, L, P, seed)
+    tp.test_medium_fraction(oracle1, 64, 0.3, 1)
