@@ -53,6 +53,20 @@ class ising_averages(C.Structure):
                 ("abs_m", C.c_double), ("m2", C.c_double)]
 
 
+class perc_params(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("porosity", C.c_double), ("seed", C.c_uint64), ("source", C.c_uint32),
+                ("i0", C.c_uint32), ("j0", C.c_uint32)]
+
+
+class perc_result(C.Structure):
+    _fields_ = [("pores", C.c_uint64), ("invaded", C.c_uint64), ("passes", C.c_int32), ("spans", C.c_uint32),
+                ("launches", C.c_uint32), ("pad", C.c_uint32), ("arrival_hash", C.c_uint64)]
+
+
+PERC_SOURCE_TOP_ROW = 0
+PERC_SOURCE_POINT = 1
+
+
 class IsingError(RuntimeError):
     def __init__(self, code, what=""):
         self.code = code
@@ -85,6 +99,12 @@ SIGNATURES = {
     "ising_demon_sum": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
     "ising_copy_demons": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ising_destroy": (C.c_int, [C.c_void_p]),
+    "perc_create": (C.c_int, [C.POINTER(perc_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "perc_run": (C.c_int, [C.c_void_p]),
+    "perc_result_get": (C.c_int, [C.c_void_p, C.POINTER(perc_result), C.c_uint32]),
+    "perc_copy_medium": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "perc_copy_arrival": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
+    "perc_destroy": (C.c_int, [C.c_void_p]),
     "ising_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -254,6 +274,39 @@ def ising_copy_demons(ctx, L):
 
 def ising_destroy(ctx):
     _check(lib().ising_destroy(ctx), "ising_destroy")
+
+
+def perc_create(L, porosity, seed=0, source=PERC_SOURCE_TOP_ROW, i0=0, j0=0, stream=None):
+    p = perc_params(int(L), float(porosity), int(seed), int(source), int(i0), int(j0))
+    out = C.c_void_p()
+    _check(lib().perc_create(C.byref(p), stream, C.byref(out)), "perc_create")
+    return out.value
+
+
+def perc_run(ctx):
+    _check(lib().perc_run(ctx), "perc_run")
+
+
+def perc_result_get(ctx, want_hash=False):
+    r = perc_result()
+    _check(lib().perc_result_get(ctx, C.byref(r), 1 if want_hash else 0), "perc_result_get")
+    return r
+
+
+def perc_copy_medium(ctx, L):
+    out = np.empty((L, L), dtype=np.uint8)
+    _check(lib().perc_copy_medium(ctx, out.ctypes.data, out.size), "perc_copy_medium")
+    return out
+
+
+def perc_copy_arrival(ctx, L):
+    out = np.empty((L, L), dtype=np.int32)
+    _check(lib().perc_copy_arrival(ctx, out.ctypes.data, out.size), "perc_copy_arrival")
+    return out
+
+
+def perc_destroy(ctx):
+    _check(lib().perc_destroy(ctx), "perc_destroy")
 
 
 def ising_strerror(code):

@@ -1,0 +1,266 @@
+// HIP kernels of the gfx950 site-percolation engine (Section 2.3 of Tomov
+// et al. 2003): porosity draw, then invasion of the medium from the source.
+//
+// The paper's GPU program spreads the cluster by one pass over the whole
+// lattice per invasion step, so a medium whose cluster needs D steps costs
+// D full passes. Here the arrival pass of every site (its breadth-first
+// distance from the source through pores) is computed directly by
+// relaxation, arrival = min(arrival, 1 + min over the four neighbours), in
+// 64 x 64 tiles held in LDS: a workgroup relaxes its tile to a local fixed
+// point (many steps per HBM round trip), and a tile is revisited only when
+// a neighbouring tile changed the sites on their shared edge. Values only
+// ever decrease and every read value is an upper bound of the true
+// distance, so the unique fixed point, reached when no tile is queued, is
+// exact whatever the timing of concurrent reads.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+#include "perc_launch.hpp"
+
+namespace perc {
+
+namespace {
+
+constexpr uint32_t kSide = kTile + 2;          // tile plus one-site halo
+constexpr uint32_t kMaxIters = 1u << 14;       // per visit; a tile still changing is queued again
+
+// LDS accesses of the relaxation: other waves update neighbouring rows
+// concurrently, so reads and writes are relaxed atomics (plain ds_read /
+// ds_write on the hardware) and may see either value.
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// New arrival of a site from its current value and its four neighbours
+// (solid neighbours hold 0xffffffff, unreached ones kUnreached, and both
+// give kUnreached + 1 > any reachable value).
+__device__ __forceinline__ uint32_t relax1(uint32_t cur, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    uint32_t m = min(min(a, b), min(c, d));
+    m = min(m, kUnreached) + 1u;
+    return min(cur, m);
+}
+
+__device__ __forceinline__ void push(const WorkLists& w, uint32_t par, uint32_t lout, uint32_t tile) {
+    uint32_t* q = w.queued[par];
+    if (atomicExch(&q[tile], 1u) == 0u) {
+        const uint32_t pos = atomicAdd(&w.len[lout], 1u);
+        w.list[par][pos] = tile;
+    }
+}
+
+}  // namespace
+
+// Porosity draw and initial arrival: one Philox call per group of four
+// row-major sites. Counts pores into st->pores.
+__global__ void __launch_bounds__(kThreads) k_perc_draw(uint8_t* pore, uint32_t* arr, uint32_t L, uint64_t N,
+                                                        uint64_t pthr, uint32_t k0, uint32_t k1, uint32_t source,
+                                                        uint32_t i0, uint32_t j0, Stats* st) {
+    const uint64_t groups = (N + 3) / 4;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t cnt = 0;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < groups; g += stride) {
+        const uint4 r = ising::philox((uint32_t)g, 0u, 0u, 2u, k0, k1);
+        const uint32_t u[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) {
+            const uint64_t ord = 4 * g + b;
+            if (ord >= N) break;
+            const uint32_t p = (uint64_t)u[b] < pthr ? 1u : 0u;
+            const uint32_t i = (uint32_t)(ord / L), j = (uint32_t)(ord - (uint64_t)i * L);
+            const bool src = source == 0u ? i == 0u : (i == i0 && j == j0);
+            pore[ord] = (uint8_t)p;
+            arr[ord] = p ? (src ? 0u : kUnreached) : kSolid;
+            cnt += p;
+        }
+    }
+    const uint32_t s = ising::wave_sum_u32(cnt);
+    if ((threadIdx.x & 63u) == 0u && s) atomicAdd(&st->pores, (unsigned long long)s);
+}
+
+// Initial work list: the tiles holding the source, and cleared counters.
+__global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, uint32_t n_tx, uint32_t source, uint32_t i0,
+                                                        uint32_t j0) {
+    uint32_t* q = w.queued[0];
+    if (source == 0u) {
+        for (uint32_t t = threadIdx.x; t < n_tx; t += blockDim.x) {
+            w.list[0][t] = t;
+            q[t] = 1u;
+        }
+        if (threadIdx.x == 0) w.len[0] = n_tx;
+    } else if (threadIdx.x == 0) {
+        const uint32_t t = (i0 / kTile) * n_tx + j0 / kTile;
+        w.list[0][0] = t;
+        q[t] = 1u;
+        w.len[0] = 1u;
+    }
+    if (threadIdx.x == 0) {
+        w.len[1] = 0u;
+        w.len[2] = 0u;
+    }
+}
+
+// One relaxation launch (number k of the run): relax every listed tile to
+// its local fixed point, write back what changed, queue the neighbours
+// whose shared edge changed.
+__global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty,
+                                                         WorkLists w, uint32_t pin, uint32_t lin, uint32_t lout,
+                                                         uint32_t lclr) {
+    __shared__ uint32_t d[kSide * kSide];
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.len[lclr] = 0u;
+    const uint32_t n = w.len[lin];
+    const uint32_t x = threadIdx.x & (kTile - 1);
+    const uint32_t y0 = (threadIdx.x / kTile) * kStrip;
+    uint32_t* q_in = w.queued[pin];
+    for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+        const uint32_t tile = w.list[pin][e];
+        const uint32_t ty = tile / n_tx, tx = tile - ty * n_tx;
+        const int64_t gi0 = (int64_t)ty * kTile - 1, gj0 = (int64_t)tx * kTile - 1;  // halo origin
+        if (threadIdx.x == 0) q_in[tile] = 0u;
+        for (uint32_t k = threadIdx.x; k < kSide * kSide; k += blockDim.x) {
+            const uint32_t yy = k / kSide, xx = k - yy * kSide;
+            const int64_t gi = gi0 + yy, gj = gj0 + xx;
+            uint32_t v = kSolid;
+            if (gi >= 0 && gj >= 0 && gi < (int64_t)L && gj < (int64_t)L) v = arr[(size_t)gi * L + (size_t)gj];
+            d[k] = v;
+        }
+        __syncthreads();
+        uint32_t orig[kStrip];
+#pragma unroll
+        for (uint32_t r = 0; r < kStrip; ++r) orig[r] = d[(y0 + r + 1) * kSide + x + 1];
+        uint32_t* col = d + x + 1;  // this thread's column; row yy at col[yy * kSide]
+        uint32_t iters = 0;
+        int go;
+        do {
+            bool ch = false;
+            // top to bottom along the strip, then bottom to top
+            uint32_t up = lds_ld(col + y0 * kSide);
+            uint32_t cur = lds_ld(col + (y0 + 1) * kSide);
+#pragma unroll
+            for (uint32_t r = 0; r < kStrip; ++r) {
+                const uint32_t yy = y0 + 1 + r;
+                const uint32_t dn = lds_ld(col + (yy + 1) * kSide);
+                if (cur != kSolid) {
+                    const uint32_t nv = relax1(cur, up, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1));
+                    if (nv < cur) {
+                        lds_st(col + yy * kSide, nv);
+                        cur = nv;
+                        ch = true;
+                    }
+                }
+                up = cur;
+                cur = dn;
+            }
+            uint32_t dn = lds_ld(col + (y0 + kStrip + 1) * kSide);
+            cur = lds_ld(col + (y0 + kStrip) * kSide);
+#pragma unroll
+            for (uint32_t r = 0; r < kStrip; ++r) {
+                const uint32_t yy = y0 + kStrip - r;
+                const uint32_t upv = lds_ld(col + (yy - 1) * kSide);
+                if (cur != kSolid) {
+                    const uint32_t nv = relax1(cur, upv, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1));
+                    if (nv < cur) {
+                        lds_st(col + yy * kSide, nv);
+                        cur = nv;
+                        ch = true;
+                    }
+                }
+                dn = cur;
+                cur = upv;
+            }
+            ++iters;
+            go = __syncthreads_or(ch);
+        } while (go && iters < kMaxIters);
+        bool top = false, bot = false, lft = false, rgt = false;
+#pragma unroll
+        for (uint32_t r = 0; r < kStrip; ++r) {
+            const uint32_t v = d[(y0 + r + 1) * kSide + x + 1];
+            if (v != orig[r]) {
+                // sites beyond the lattice are solid and never change
+                arr[(size_t)(gi0 + 1 + y0 + r) * L + (size_t)(gj0 + 1 + x)] = v;
+                top |= (y0 + r) == 0u;
+                bot |= (y0 + r) == kTile - 1;
+                lft |= x == 0u;
+                rgt |= x == kTile - 1;
+            }
+        }
+        top = __syncthreads_or(top);
+        bot = __syncthreads_or(bot);
+        lft = __syncthreads_or(lft);
+        rgt = __syncthreads_or(rgt);
+        if (threadIdx.x == 0) {
+            const uint32_t par = pin ^ 1u;
+            if (top && ty > 0) push(w, par, lout, tile - n_tx);
+            if (bot && ty + 1 < n_ty) push(w, par, lout, tile + n_tx);
+            if (lft && tx > 0) push(w, par, lout, tile - 1);
+            if (rgt && tx + 1 < n_tx) push(w, par, lout, tile + 1);
+            if (go) push(w, par, lout, tile);  // visit cap reached: not yet at its fixed point
+        }
+    }
+}
+
+// Final pass: unreached pores become -1; count the cluster, its largest
+// arrival and which lattice edges it touches.
+__global__ void __launch_bounds__(kThreads) k_perc_finish(uint32_t* arr, uint32_t L, uint64_t N, Stats* st) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t cnt = 0, mx = 0, edges = 0;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < N; k += stride) {
+        const uint32_t v = arr[k];
+        if (v == kUnreached) {
+            arr[k] = kSolid;
+        } else if (v != kSolid) {
+            const uint32_t i = (uint32_t)(k / L), j = (uint32_t)(k - (uint64_t)i * L);
+            ++cnt;
+            mx = max(mx, v);
+            edges |= (i == 0u ? 1u : 0u) | (i == L - 1 ? 2u : 0u) | (j == 0u ? 4u : 0u) | (j == L - 1 ? 8u : 0u);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        cnt += __shfl_xor(cnt, off, 64);
+        mx = max(mx, (uint32_t)__shfl_xor(mx, off, 64));
+        edges |= (uint32_t)__shfl_xor(edges, off, 64);
+    }
+    if ((threadIdx.x & 63u) == 0u) {
+        if (cnt) atomicAdd(&st->invaded, (unsigned long long)cnt);
+        if (mx) atomicMax(&st->max_arrival, mx);
+        if (edges) atomicOr(&st->edges, edges);
+    }
+}
+
+static uint32_t grid_for(uint64_t n) {
+    const uint64_t b = (n + kThreads - 1) / kThreads;
+    return (uint32_t)(b > 8192 ? 8192 : (b ? b : 1));
+}
+
+hipError_t launch_draw(uint8_t* pore, uint32_t* arr, uint32_t L, uint64_t pthr, uint32_t k0, uint32_t k1,
+                       uint32_t source, uint32_t i0, uint32_t j0, Stats* stats, hipStream_t s) {
+    const uint64_t N = (uint64_t)L * L;
+    k_perc_draw<<<grid_for((N + 3) / 4), kThreads, 0, s>>>(pore, arr, L, N, pthr, k0, k1, source, i0, j0, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_lists(const WorkLists& w, uint32_t n_tx, uint32_t n_tiles, uint32_t source, uint32_t i0,
+                             uint32_t j0, hipStream_t s) {
+    (void)n_tiles;
+    k_perc_seed<<<1, kThreads, 0, s>>>(w, n_tx, source, i0, j0);
+    return hipGetLastError();
+}
+
+hipError_t launch_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty, const WorkLists& w, uint64_t k,
+                        uint32_t grid, hipStream_t s) {
+    k_perc_relax<<<grid, kThreads, 0, s>>>(arr, L, n_tx, n_ty, w, (uint32_t)(k % 2), (uint32_t)(k % 3),
+                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3));
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(uint32_t* arr, uint32_t L, Stats* stats, hipStream_t s) {
+    const uint64_t N = (uint64_t)L * L;
+    k_perc_finish<<<grid_for(N), kThreads, 0, s>>>(arr, L, N, stats);
+    return hipGetLastError();
+}
+
+}  // namespace perc

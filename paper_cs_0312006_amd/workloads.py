@@ -88,3 +88,23 @@ def random_demons(L, seed, hi):
 # with empty demons, so the total energy is near 0 and the demons settle at
 # a temperature of about 2.56 J.
 CREUTZ = Run(L=32768, seed=11, p_up=0.5, sweeps=500)
+
+
+@dataclass(frozen=True)
+class Medium:
+    """A porous medium and its invasion source (Section 2.3)."""
+    L: int
+    porosity: float
+    seed: int = 0
+    source: int = 0  # 0: every pore of row 0; 1: the point (i0, j0)
+    i0: int = 0
+    j0: int = 0
+
+    def sites(self):
+        return self.L * self.L
+
+
+# The medium of the paper's Figure 3 (512 x 512, porosity 0.6), and the
+# same porosity at the headline lattice size.
+PERC_FIG3 = Medium(L=512, porosity=0.6, seed=3)
+PERC_HEADLINE = Medium(L=32768, porosity=0.6, seed=11)

@@ -9,13 +9,19 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "ising.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w ]+\**\s*\**\b(ising_\w+)\s*\(", text, re.M)))
+    """Every function declared in include/*.h."""
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:const\s+)?[\w ]+\**\s*\**\b((?:ising|perc)_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +33,7 @@ def b():
 
 def test_header_declares_the_four_core_calls():
     names = declared_functions()
-    for core in ("ising_create", "ising_sweep", "ising_observables", "ising_destroy"):
+    for core in ("ising_create", "ising_sweep", "ising_observables", "ising_destroy", "perc_create", "perc_run"):
         assert core in names
 
 

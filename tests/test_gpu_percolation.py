@@ -1,0 +1,105 @@
+"""GPU parity of the percolation engine (Section 2.3) through the C ABI:
+medium, arrival map and summary bit-exact against the oracle on seeded
+media; at the full 32768^2 size, sampled draws against the NumPy Philox and
+the local conditions that fix breadth-first arrival passes uniquely."""
+import numpy as np
+import pytest
+
+from oracle import mini
+from paper_cs_0312006_amd import workloads as W
+from tests import gpu_util as G
+from tests.perc_checks import check_arrival_local
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_cs_0312006_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def o():
+    from oracle import ref
+    orc = ref.Oracle()
+    orc.set_threads(G.host_threads())
+    return orc
+
+
+def _gpu(b, m, want_hash=True):
+    ctx = b.perc_create(m.L, m.porosity, m.seed, m.source, m.i0, m.j0)
+    try:
+        b.perc_run(ctx)
+        r = b.perc_result_get(ctx, want_hash)
+        return r, b.perc_copy_medium(ctx, m.L), b.perc_copy_arrival(ctx, m.L)
+    finally:
+        b.perc_destroy(ctx)
+
+
+CASES = [
+    W.Medium(1, 0.5, 1), W.Medium(1, 1.0, 1, 1, 0, 0), W.Medium(7, 0.6, 2), W.Medium(63, 0.6, 3),
+    W.Medium(64, 0.5927, 4), W.Medium(65, 0.65, 5, 1, 32, 40), W.Medium(100, 0.7, 6, 1, 99, 0),
+    W.Medium(128, 0.55, 7), W.Medium(130, 1.0, 8), W.Medium(64, 0.0, 9), W.Medium(257, 0.6, 10),
+    W.PERC_FIG3, W.Medium(512, 0.5927, 12, 1, 256, 256), W.Medium(1000, 0.6, 13), W.Medium(2048, 0.62, 14),
+]
+
+
+@pytest.mark.parametrize("m", CASES, ids=lambda m: f"L{m.L}-P{m.porosity}-s{m.seed}-src{m.source}")
+def test_percolation_parity(b, o, m):
+    G.log(f"percolation {m}")
+    r, pore, arr = _gpu(b, m)
+    pore_o = o.perc_medium(m.L, m.porosity, m.seed)
+    assert np.array_equal(pore, pore_o), "medium differs"
+    arr_o = o.perc_invade(pore_o, m.source, m.i0, m.j0)
+    if not np.array_equal(arr, arr_o):
+        bad = np.argwhere(arr != arr_o)
+        raise AssertionError(f"{len(bad)} arrival passes differ, first {bad[:5].tolist()}")
+    inv, mx, sp = o.perc_summary(arr_o)
+    assert (r.pores, r.invaded, r.passes, r.spans) == (int(pore_o.sum()), inv, mx, sp)
+    assert r.arrival_hash == o.fnv1a64(arr_o)
+
+
+def test_rerun_and_errors(b):
+    m = W.Medium(96, 0.6, 5)
+    ctx = b.perc_create(m.L, m.porosity, m.seed)
+    try:
+        with pytest.raises(b.IsingError) as e:
+            b.perc_result_get(ctx)
+        assert e.value.code == b.ISING_ESTATE
+        b.perc_run(ctx)
+        r1 = b.perc_result_get(ctx, True)
+        b.perc_run(ctx)
+        r2 = b.perc_result_get(ctx, True)
+        assert (r1.arrival_hash, r1.invaded, r1.passes) == (r2.arrival_hash, r2.invaded, r2.passes)
+    finally:
+        b.perc_destroy(ctx)
+    for kw in (dict(L=0, porosity=0.5), dict(L=65537, porosity=0.5), dict(L=8, porosity=1.5),
+               dict(L=8, porosity=float("nan")), dict(L=8, porosity=0.5, source=2),
+               dict(L=8, porosity=0.5, source=1, i0=8)):
+        with pytest.raises(b.IsingError) as e:
+            b.perc_create(**kw)
+        assert e.value.code == b.ISING_EINVAL
+
+
+def test_full_size_medium_and_arrival(b):
+    """32768 x 32768 at porosity 0.6 (the configuration bench.py times): 4096
+    sampled sites of the medium equal the NumPy Philox draw; the arrival map
+    satisfies the local conditions of breadth-first distances; the summary
+    equals the one recomputed from the copied maps."""
+    m = W.PERC_HEADLINE
+    G.log(f"percolation full size {m}")
+    r, pore, arr = _gpu(b, m, want_hash=False)
+    rng = np.random.default_rng(0)
+    ords = rng.integers(0, m.L * m.L, size=4096, dtype=np.uint64)
+    words = mini.philox4x32_10(ords >> np.uint64(2), 0, 0, 2, m.seed & 0xFFFFFFFF, m.seed >> 32)
+    u = np.choose((ords & np.uint64(3)).astype(np.int64), words)
+    expect = (u < np.uint64(int(np.floor(m.porosity * 2.0 ** 32)))).astype(np.uint8)
+    assert np.array_equal(pore.ravel()[ords.astype(np.int64)], expect)
+    G.log("percolation full size: local conditions")
+    check_arrival_local(pore, arr, m.source)
+    inv = arr >= 0
+    spans = (1 if inv[0].any() and inv[-1].any() else 0) | (2 if inv[:, 0].any() and inv[:, -1].any() else 0)
+    assert (r.pores, r.invaded, r.passes, r.spans) == (int(pore.sum(dtype=np.int64)), int(inv.sum()),
+                                                      int(arr.max()), spans)

@@ -10,6 +10,8 @@ import pytest
 from scipy import ndimage
 from scipy.sparse import csgraph, csr_matrix
 
+from tests.perc_checks import check_arrival_local
+
 
 def _pore_graph(pore):
     """Sparse adjacency of pores (4-neighbour, open boundaries)."""
@@ -129,3 +131,19 @@ def test_spanning_threshold_near_pc(oracle):
     th = [_span_threshold(oracle, 128, s) for s in range(120)]
     med = float(np.median(th))
     assert abs(med - 0.592746) < 0.008, med
+
+
+def test_local_check_rejects_wrong_maps(oracle):
+    """The local check itself: it passes the oracle's map and fails maps
+    with one site off by one, one pore dropped, or one extra zero."""
+    pore = oracle.perc_medium(200, 0.65, 3)
+    arr = oracle.perc_invade(pore, 0)
+    check_arrival_local(pore, arr, 0, rows=37)
+    k = np.argwhere(arr > 3)[10]
+    for mutate in (lambda a: a.__setitem__(tuple(k), a[tuple(k)] + 1),
+                   lambda a: a.__setitem__(tuple(k), -1),
+                   lambda a: a.__setitem__(tuple(k), 0)):
+        bad = arr.copy()
+        mutate(bad)
+        with pytest.raises(AssertionError):
+            check_arrival_local(pore, bad, 0, rows=37)
