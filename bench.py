@@ -6,9 +6,11 @@ start with seed 11; the lattice (1 GiB of int8 spins in colour planes) is
 resident in HBM before the timed region. Prints one JSON line.
 
 Also reported: the other three 32768^2 runs (h = 0.1, cold starts), the
-batched configuration (1024 lattices of uneven size in one persistent
-launch, against one launch per lattice on a sample), the oracle timed on the
-host cores (cpu_baseline), and roofline figures for the dominant kernel.
+batched configuration (1024 lattices of uneven size, against one launch per
+lattice on a sample), the served request stream, Creutz demon sweeps,
+percolation media, the vector-op and transfer micro-benchmarks, the oracle
+timed on the host cores (cpu_baseline), and roofline figures for the
+dominant kernel.
 """
 import argparse
 import json
@@ -183,6 +185,143 @@ def run_served(rates, count, epoch_sweeps):
     return out
 
 
+def run_creutz(b, torch, stream, sweeps, metropolis_value):
+    """Creutz demon sweeps of the 32768^2 hot start with empty demons
+    (Section 2.2's random-number-free alternative), timed like the headline;
+    algorithmic traffic 4 B per site and sweep (spin and demon bytes, each
+    read and written once)."""
+    from paper_cs_0312006_amd import workloads as W
+    run = W.CREUTZ
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
+    try:
+        b.ising_creutz_init(ctx, None, 0)
+        obs0, _, _ = b.ising_observables(ctx, 0)
+        b.ising_creutz_sweep(ctx, 2)
+        b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.ising_creutz_sweep(ctx, sweeps)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        demons = b.ising_demon_sum(ctx)
+    finally:
+        b.ising_destroy(ctx)
+    N = run.L * run.L
+    value = N * sweeps / ms / 1e6
+    achieved = 4.0 * N / (ms / sweeps * 1e-3) / 1e9
+    t_demon = 4.0 / __import__("math").log1p(N / demons) if demons else None
+    return {"workload": f"creutz demons {run.L}x{run.L}, hot start seed {run.seed}, demons 0",
+            "sweeps": sweeps, "value": value, "unit": "site updates/ns", "ms_per_sweep": ms / sweeps,
+            "vs_metropolis_headline": value / metropolis_value,
+            "energy_conserved": bool(-obs.bond_sum + 4 * demons == -obs0.bond_sum),
+            "demon_temperature": t_demon,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_creutz_words (two passes per sweep)",
+                         "algorithmic_bytes_per_sweep": 4.0 * N}}
+
+
+def run_percolation(b, cpu=True):
+    """Porous media of Section 2.3 (porosity 0.6): the paper's Figure 3
+    size and the headline lattice size; the oracle (plain breadth-first
+    search) timed on an 8192^2 medium of the same kind."""
+    from paper_cs_0312006_amd import workloads as W
+    out = []
+    for m in (W.PERC_FIG3, W.PERC_HEADLINE):
+        ctx = b.perc_create(m.L, m.porosity, m.seed, m.source, m.i0, m.j0)
+        try:
+            b.perc_run(ctx)  # warm
+            t0 = time.perf_counter()
+            b.perc_run(ctx)
+            s = time.perf_counter() - t0
+            r = b.perc_result_get(ctx)
+        finally:
+            b.perc_destroy(ctx)
+        N = m.L * m.L
+        out.append({"workload": f"percolation {m.L}x{m.L} porosity {m.porosity} seed {m.seed}, top-row invasion",
+                    "ms": s * 1e3, "value": N / s / 1e9, "unit": "medium sites/ns (draw + invasion to steady state)",
+                    "passes_to_steady_state": r.passes, "invaded": r.invaded, "spans": r.spans,
+                    "relax_launches": r.launches, "tile_visits": r.tile_visits,
+                    "relax_iterations_per_visit": r.tile_iterations / max(1, r.tile_visits),
+                    "paper_method_equivalent": {
+                        "value": N * max(1, r.passes) / s / 1e9,
+                        "unit": "site-passes/ns (one full pass per invasion step, as in Section 2.3)"}})
+    res = {"runs": out}
+    if cpu:
+        from oracle import ref
+        o = ref.Oracle()
+        cores = min(16, host_cores())
+        o.set_threads(cores)
+        L = 8192
+        t0 = time.perf_counter()
+        pore = o.perc_medium(L, 0.6, 11)
+        t1 = time.perf_counter()
+        arr = o.perc_invade(pore, 0)
+        t2 = time.perf_counter()
+        res["cpu_baseline"] = {"value": L * L / (t2 - t0) / 1e9, "unit": "medium sites/ns", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{L}x{L} medium, porosity 0.6: draw {t1 - t0:.2f} s on {cores} threads, "
+                                         f"breadth-first invasion {t2 - t1:.2f} s on one thread; "
+                                         f"{int((arr >= 0).sum())} sites invaded"}
+    return res
+
+
+def run_micro(b, torch, stream):
+    """The paper's GPU calibration on the MI355X: Table 2's vector ops on
+    float vectors of 4 values per site (the paper's 256^2 and 512^2, and a
+    1 GiB vector), and Table 5's whole-lattice and border-only transfers
+    between pinned host memory and HBM."""
+    ops = ["=", "+", "-", "*", "/", "sin", "cos", "log", "exp"]
+    vec = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for side in (256, 512, 8192):
+        n = 4 * side * side
+        a = torch.rand(n, device="cuda") + 0.5
+        c = torch.rand(n, device="cuda") + 0.5
+        reps = 200 if side < 8192 else 10
+        for op in ops:
+            torch.cuda.synchronize()
+            b.mb_vector_op(op, a.data_ptr(), c.data_ptr(), n, stream.cuda_stream)
+            if op in ("sin", "cos", "log", "exp"):
+                a.uniform_(0.5, 1.5)  # keep log and exp in range
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                b.mb_vector_op(op, a.data_ptr(), c.data_ptr(), n, stream.cuda_stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = 4 * n * (2 if op == "=" else (3 if op in "+-*/" else 2))
+            vec.append({"op": op, "lattice": side, "floats": n, "s": ms * 1e-3, "GB_per_s": nbytes / ms / 1e6})
+        del a, c
+    tr = []
+    for side in (64, 128, 256, 512, 8192):
+        elem = 16  # a float4 texel per site, as the paper's textures
+        host = torch.empty(side * side * elem, dtype=torch.uint8).pin_memory()
+        dev = torch.empty(side * side * elem, dtype=torch.uint8, device="cuda")
+        for name, direction, border in (("read bdr", 1, True), ("read all", 1, False),
+                                        ("write bdr", 0, True), ("write all", 0, False)):
+            dst, src = (host, dev) if direction == 1 else (dev, host)
+            reps = 50 if side < 8192 else 5
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(reps):
+                b.mb_copy_lattice(dst.data_ptr(), src.data_ptr(), side, elem, direction, border, stream.cuda_stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            nbytes = (4 * side - 4 if border and side > 2 else side * side) * elem
+            tr.append({"op": name, "lattice": side, "bytes": nbytes, "s": ms * 1e-3, "MB_per_s": nbytes / ms / 1e3})
+        del host, dev
+    copy_gbs = max(v["GB_per_s"] for v in vec if v["op"] == "=" and v["lattice"] == 8192)
+    return {"vector_ops": vec, "transfers": tr, "achievable_hbm_copy_GB_per_s": copy_gbs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +339,7 @@ def main():
     ap.add_argument("--served-rates", type=str, default="100,1000,5000")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--epoch-sweeps", type=int, default=64)
+    ap.add_argument("--creutz-sweeps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -287,6 +427,11 @@ def main():
 
     if not args.no_extra and not args.no_served:
         out["served"] = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
+
+    if not args.no_extra:
+        out["creutz"] = run_creutz(b, torch, stream, args.creutz_sweeps, value)
+        out["percolation"] = run_percolation(b, cpu=not args.no_cpu)
+        out["micro"] = run_micro(b, torch, stream)
 
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

@@ -47,8 +47,11 @@ typedef struct perc_result {
     uint64_t invaded;       /* sites in the final cluster */
     int32_t passes;         /* passes to the steady state = max arrival (0 if the cluster is empty) */
     uint32_t spans;         /* bit 0: cluster holds sites of rows 0 and L-1; bit 1: of columns 0 and L-1 */
-    uint32_t launches;      /* relaxation launches the engine used (work measure, not a paper quantity) */
+    /* work measures of the engine (not paper quantities) */
+    uint32_t launches;         /* relaxation launches */
     uint32_t pad;
+    uint64_t tile_visits;      /* 64 x 64 tiles relaxed, summed over launches */
+    uint64_t tile_iterations;  /* relaxation iterations, summed over tile visits */
     uint64_t arrival_hash;  /* FNV-1a-64 of the int32 arrival map, little-endian row-major (opt-in) */
 } perc_result;
 

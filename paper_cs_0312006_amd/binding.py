@@ -60,7 +60,8 @@ class perc_params(C.Structure):
 
 class perc_result(C.Structure):
     _fields_ = [("pores", C.c_uint64), ("invaded", C.c_uint64), ("passes", C.c_int32), ("spans", C.c_uint32),
-                ("launches", C.c_uint32), ("pad", C.c_uint32), ("arrival_hash", C.c_uint64)]
+                ("launches", C.c_uint32), ("pad", C.c_uint32), ("tile_visits", C.c_uint64),
+                ("tile_iterations", C.c_uint64), ("arrival_hash", C.c_uint64)]
 
 
 PERC_SOURCE_TOP_ROW = 0
@@ -105,6 +106,9 @@ SIGNATURES = {
     "perc_copy_medium": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "perc_copy_arrival": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "perc_destroy": (C.c_int, [C.c_void_p]),
+    "mb_vector_op": (C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "mb_copy_lattice": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
+                                  C.c_void_p]),
     "ising_strerror": (C.c_char_p, [C.c_int]),
 }
 
@@ -307,6 +311,22 @@ def perc_copy_arrival(ctx, L):
 
 def perc_destroy(ctx):
     _check(lib().perc_destroy(ctx), "perc_destroy")
+
+
+MB_OPS = {"=": 0, "+": 1, "-": 2, "*": 3, "/": 4, "sin": 5, "cos": 6, "log": 7, "exp": 8}
+MB_HOST_TO_DEVICE = 0
+MB_DEVICE_TO_HOST = 1
+
+
+def mb_vector_op(op, a_ptr, c_ptr, n, stream=None):
+    """op: a key of MB_OPS or its code; a_ptr / c_ptr: device addresses."""
+    code = MB_OPS[op] if isinstance(op, str) else int(op)
+    _check(lib().mb_vector_op(code, a_ptr, c_ptr, int(n), stream), "mb_vector_op")
+
+
+def mb_copy_lattice(dst_ptr, src_ptr, L, elem, direction, border=False, stream=None):
+    _check(lib().mb_copy_lattice(dst_ptr, src_ptr, int(L), int(elem), int(direction), 1 if border else 0, stream),
+           "mb_copy_lattice")
 
 
 def ising_strerror(code):

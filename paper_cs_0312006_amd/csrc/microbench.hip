@@ -1,0 +1,114 @@
+// Vector-operation and host-transfer micro-benchmarks (include/microbench.h):
+// the MI355X counterparts of the paper's GPU calibration (Table 2: one pass
+// of a simple operation over float vectors; Table 5: whole-lattice and
+// border-only transfers between host and GPU).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "microbench.h"
+
+namespace {
+
+constexpr uint32_t kThreads = 256;
+
+template <uint32_t OP>
+__device__ __forceinline__ float apply(float a, float c) {
+    if constexpr (OP == MB_OP_COPY) return c;
+    if constexpr (OP == MB_OP_ADD) return a + c;
+    if constexpr (OP == MB_OP_SUB) return a - c;
+    if constexpr (OP == MB_OP_MUL) return a * c;
+    if constexpr (OP == MB_OP_DIV) return a / c;
+    if constexpr (OP == MB_OP_SIN) return sinf(a);
+    if constexpr (OP == MB_OP_COS) return cosf(a);
+    if constexpr (OP == MB_OP_LOG) return logf(a);
+    return expf(a);
+}
+
+// Grid-stride over float4 (n4 of them), then the scalar tail.
+template <uint32_t OP>
+__global__ void __launch_bounds__(kThreads) k_vec(float* __restrict__ a, const float* __restrict__ c, size_t n) {
+    constexpr bool reads_a = OP != MB_OP_COPY;
+    constexpr bool reads_c = OP <= MB_OP_DIV;
+    const size_t n4 = n / 4;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    float4* a4 = reinterpret_cast<float4*>(a);
+    const float4* c4 = reinterpret_cast<const float4*>(c);
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n4; k += stride) {
+        float4 x = reads_a ? a4[k] : float4{0.f, 0.f, 0.f, 0.f};
+        const float4 y = reads_c ? c4[k] : float4{0.f, 0.f, 0.f, 0.f};
+        x.x = apply<OP>(x.x, y.x);
+        x.y = apply<OP>(x.y, y.y);
+        x.z = apply<OP>(x.z, y.z);
+        x.w = apply<OP>(x.w, y.w);
+        a4[k] = x;
+    }
+    for (size_t k = 4 * n4 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += stride)
+        a[k] = apply<OP>(reads_a ? a[k] : 0.f, reads_c ? c[k] : 0.f);
+}
+
+template <uint32_t OP>
+hipError_t launch(float* a, const float* c, size_t n, hipStream_t s) {
+    size_t blocks = (n / 4 + kThreads - 1) / kThreads;
+    if (blocks > 8192) blocks = 8192;  // 32 waves per CU, grid-stride beyond
+    if (blocks == 0) blocks = 1;
+    k_vec<OP><<<(uint32_t)blocks, kThreads, 0, s>>>(a, c, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int mb_vector_op(uint32_t op, float* a, const float* c, size_t n, void* stream) {
+    if (op > MB_OP_EXP || !a) return ISING_EINVAL;
+    if (op <= MB_OP_DIV && !c) return ISING_EINVAL;
+    if (((uintptr_t)a & 15u) || ((uintptr_t)c & 15u)) return ISING_EINVAL;
+    if (n == 0) return ISING_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    switch (op) {
+        case MB_OP_COPY: e = launch<MB_OP_COPY>(a, c, n, s); break;
+        case MB_OP_ADD: e = launch<MB_OP_ADD>(a, c, n, s); break;
+        case MB_OP_SUB: e = launch<MB_OP_SUB>(a, c, n, s); break;
+        case MB_OP_MUL: e = launch<MB_OP_MUL>(a, c, n, s); break;
+        case MB_OP_DIV: e = launch<MB_OP_DIV>(a, c, n, s); break;
+        case MB_OP_SIN: e = launch<MB_OP_SIN>(a, c, n, s); break;
+        case MB_OP_COS: e = launch<MB_OP_COS>(a, c, n, s); break;
+        case MB_OP_LOG: e = launch<MB_OP_LOG>(a, c, n, s); break;
+        default: e = launch<MB_OP_EXP>(a, c, n, s); break;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return ISING_EDEVICE;
+    }
+    return ISING_OK;
+}
+
+int mb_copy_lattice(void* dst, const void* src, uint32_t L, uint32_t elem, uint32_t direction, int border,
+                    void* stream) {
+    if (!dst || !src || L == 0 || elem == 0 || direction > MB_DEVICE_TO_HOST) return ISING_EINVAL;
+    const hipMemcpyKind kind = direction == MB_HOST_TO_DEVICE ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t row = (size_t)L * elem;
+    char* d = static_cast<char*>(dst);
+    const char* c = static_cast<const char*>(src);
+    hipError_t e = hipSuccess;
+    if (!border || L <= 2) {
+        e = hipMemcpyAsync(d, c, row * L, kind, s);
+    } else {
+        const size_t last = (size_t)(L - 1) * row;
+        e = hipMemcpyAsync(d, c, row, kind, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(d + last, c + last, row, kind, s);
+        // columns 0 and L-1 of rows 1 .. L-2: pitched copies of one site per row
+        if (e == hipSuccess) e = hipMemcpy2DAsync(d + row, row, c + row, row, elem, L - 2, kind, s);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(d + row + row - elem, row, c + row + row - elem, row, elem, L - 2, kind, s);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return ISING_EDEVICE;
+    }
+    return ISING_OK;
+}
+
+}  // extern "C"

@@ -108,12 +108,16 @@ __global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, uint32_t n_
 // whose shared edge changed.
 __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty,
                                                          WorkLists w, uint32_t pin, uint32_t lin, uint32_t lout,
-                                                         uint32_t lclr) {
+                                                         uint32_t lclr, Stats* st) {
     __shared__ uint32_t d[kSide * kSide];
     if (blockIdx.x == 0 && threadIdx.x == 0) w.len[lclr] = 0u;
     const uint32_t n = w.len[lin];
     const uint32_t x = threadIdx.x & (kTile - 1);
     const uint32_t y0 = (threadIdx.x / kTile) * kStrip;
+    // row phase: row hr, sites hx0 .. hx0 + 15 (a wave covers 64 rows of
+    // one column segment; the 66-word row pitch spreads them over banks)
+    const uint32_t hr = threadIdx.x & (kTile - 1);
+    const uint32_t hx0 = (threadIdx.x / kTile) * kStrip;
     uint32_t* q_in = w.queued[pin];
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         const uint32_t tile = w.list[pin][e];
@@ -171,9 +175,49 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
                 dn = cur;
                 cur = upv;
             }
+            // left to right along a 16-site row segment, then right to left
+            {
+                uint32_t* row = d + (hr + 1) * kSide + hx0;  // row[c] = site column hx0 + c - 1
+                uint32_t lf = lds_ld(row);
+                uint32_t c2 = lds_ld(row + 1);
+#pragma unroll
+                for (uint32_t c = 1; c <= kStrip; ++c) {
+                    const uint32_t rt = lds_ld(row + c + 1);
+                    if (c2 != kSolid) {
+                        const uint32_t nv = relax1(c2, lf, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide));
+                        if (nv < c2) {
+                            lds_st(row + c, nv);
+                            c2 = nv;
+                            ch = true;
+                        }
+                    }
+                    lf = c2;
+                    c2 = rt;
+                }
+                uint32_t rt = lds_ld(row + kStrip + 1);
+                c2 = lds_ld(row + kStrip);
+#pragma unroll
+                for (uint32_t c = kStrip; c >= 1; --c) {
+                    const uint32_t lv = lds_ld(row + c - 1);
+                    if (c2 != kSolid) {
+                        const uint32_t nv = relax1(c2, lv, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide));
+                        if (nv < c2) {
+                            lds_st(row + c, nv);
+                            c2 = nv;
+                            ch = true;
+                        }
+                    }
+                    rt = c2;
+                    c2 = lv;
+                }
+            }
             ++iters;
             go = __syncthreads_or(ch);
         } while (go && iters < kMaxIters);
+        if (threadIdx.x == 0) {
+            atomicAdd(&st->visits, 1ull);
+            atomicAdd(&st->iterations, (unsigned long long)iters);
+        }
         bool top = false, bot = false, lft = false, rgt = false;
 #pragma unroll
         for (uint32_t r = 0; r < kStrip; ++r) {
@@ -251,9 +295,9 @@ hipError_t launch_seed_lists(const WorkLists& w, uint32_t n_tx, uint32_t n_tiles
 }
 
 hipError_t launch_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty, const WorkLists& w, uint64_t k,
-                        uint32_t grid, hipStream_t s) {
+                        uint32_t grid, Stats* stats, hipStream_t s) {
     k_perc_relax<<<grid, kThreads, 0, s>>>(arr, L, n_tx, n_ty, w, (uint32_t)(k % 2), (uint32_t)(k % 3),
-                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3));
+                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3), stats);
     return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@ struct Stats {
     unsigned long long invaded;
     uint32_t max_arrival;
     uint32_t edges;  // bit 0 row 0, bit 1 row L-1, bit 2 column 0, bit 3 column L-1
+    unsigned long long visits;      // tile visits over all relaxation launches
+    unsigned long long iterations;  // relaxation iterations summed over visits
 };
 
 // Work lists: tiles to relax in a launch. Launch k reads list[k % 2] with
@@ -35,7 +37,7 @@ hipError_t launch_draw(uint8_t* pore, uint32_t* arr, uint32_t L, uint64_t pthr, 
 hipError_t launch_seed_lists(const WorkLists& w, uint32_t n_tx, uint32_t n_tiles, uint32_t source, uint32_t i0,
                              uint32_t j0, hipStream_t s);
 hipError_t launch_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty, const WorkLists& w, uint64_t k,
-                        uint32_t grid, hipStream_t s);
+                        uint32_t grid, Stats* stats, hipStream_t s);
 hipError_t launch_finish(uint32_t* arr, uint32_t L, Stats* stats, hipStream_t s);
 
 }  // namespace perc

@@ -149,7 +149,7 @@ int perc_run(perc_ctx* c) {
     uint64_t k = 0;
     for (;;) {
         for (uint32_t g = 0; g < kLaunchGroup; ++g, ++k)
-            PERC_TRY(c, launch_relax(c->arr, p.L, c->n_tx, c->n_ty, c->w, k, c->grid, c->stream));
+            PERC_TRY(c, launch_relax(c->arr, p.L, c->n_tx, c->n_ty, c->w, k, c->grid, c->stats, c->stream));
         // tiles queued for launch k (its input list length)
         PERC_TRY(c, hipMemcpyAsync(c->h_len, c->w.len + (k % 3), sizeof(uint32_t), hipMemcpyDeviceToHost,
                                    c->stream));
@@ -198,6 +198,8 @@ int perc_result_get(perc_ctx* c, perc_result* out, uint32_t want_hash) {
     r.passes = (int32_t)st.max_arrival;
     r.spans = ((st.edges & 3u) == 3u ? 1u : 0u) | ((st.edges & 12u) == 12u ? 2u : 0u);
     r.launches = c->launches;
+    r.tile_visits = st.visits;
+    r.tile_iterations = st.iterations;
     if (want_hash) {
         std::vector<int32_t> a;
         try {

@@ -20,7 +20,7 @@ def declared_functions():
             continue
         text = open(os.path.join(INCLUDE, h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        names |= set(re.findall(r"^\s*(?:const\s+)?[\w ]+\**\s*\**\b((?:ising|perc)_\w+)\s*\(", text, re.M))
+        names |= set(re.findall(r"^\s*(?:const\s+)?[\w ]+\**\s*\**\b((?:ising|perc|mb)_\w+)\s*\(", text, re.M))
     return sorted(names)
 
 
@@ -110,3 +110,25 @@ def test_series_averages_match_plain_sums(b):
 def test_series_averages_rejects_empty(b):
     with pytest.raises(b.IsingError):
         b.ising_series_averages(np.zeros(0, np.int64), np.zeros(0, np.int64), 8)
+
+
+def test_microbench_rejects_bad_arguments(b):
+    """Argument checks that return before any device work."""
+    lib = b.lib()
+    assert lib.mb_vector_op(9, 16, 16, 4, None) == b.ISING_EINVAL     # unknown op
+    assert lib.mb_vector_op(1, None, 16, 4, None) == b.ISING_EINVAL   # no a
+    assert lib.mb_vector_op(1, 16, None, 4, None) == b.ISING_EINVAL   # c read but NULL
+    assert lib.mb_vector_op(1, 20, 16, 4, None) == b.ISING_EINVAL     # misaligned
+    assert lib.mb_vector_op(5, 16, None, 0, None) == b.ISING_OK       # empty
+    assert lib.mb_copy_lattice(None, 16, 4, 1, 0, 0, None) == b.ISING_EINVAL
+    assert lib.mb_copy_lattice(16, 16, 0, 1, 0, 0, None) == b.ISING_EINVAL
+    assert lib.mb_copy_lattice(16, 16, 4, 1, 2, 0, None) == b.ISING_EINVAL
+
+
+def test_percolation_rejects_bad_parameters(b):
+    for kw in (dict(L=0, porosity=0.5), dict(L=65537, porosity=0.5), dict(L=8, porosity=-0.1),
+               dict(L=8, porosity=float("nan")), dict(L=8, porosity=0.5, source=2),
+               dict(L=8, porosity=0.5, source=1, j0=8)):
+        with pytest.raises(b.IsingError) as e:
+            b.perc_create(**kw)
+        assert e.value.code == b.ISING_EINVAL
