@@ -244,6 +244,11 @@ int ising_destroy(ising_ctx* ctx);
 /* Static description of an error code. */
 const char* ising_strerror(int code);
 
+/* The HIP failure behind the last ISING_EDEVICE this context returned: the
+ * failing call and HIP's error name ("" if there was none). The string
+ * belongs to the context and lives until ising_destroy. */
+const char* ising_device_error(const ising_ctx* ctx);
+
 #ifdef __cplusplus
 }
 #endif

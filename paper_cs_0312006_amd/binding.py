@@ -110,6 +110,7 @@ SIGNATURES = {
     "mb_copy_lattice": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                   C.c_void_p]),
     "ising_strerror": (C.c_char_p, [C.c_int]),
+    "ising_device_error": (C.c_char_p, [C.c_void_p]),
 }
 
 _lib = None
@@ -144,8 +145,12 @@ def lib(path=None):
     return handle
 
 
-def _check(rc, what):
+def _check(rc, what, ctx=None):
     if rc != ISING_OK:
+        if rc == ISING_EDEVICE and ctx:
+            detail = lib().ising_device_error(ctx)
+            if detail:
+                what = f"{what} [{detail.decode()}]"
         raise IsingError(rc, what)
 
 
@@ -176,7 +181,7 @@ def ising_create_in(dev_ptr, nbytes, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0
 
 
 def ising_sweep(ctx, n):
-    _check(lib().ising_sweep(ctx, int(n)), "ising_sweep")
+    _check(lib().ising_sweep(ctx, int(n)), "ising_sweep", ctx)
 
 
 def ising_observables(ctx, want=0, capacity=None):
@@ -194,7 +199,7 @@ def ising_observables(ctx, want=0, capacity=None):
         bs = np.zeros(cap, dtype=np.int64)
         ms = np.zeros(cap, dtype=np.int64)
         pb, pm = bs.ctypes.data, ms.ctypes.data
-    _check(lib().ising_observables(ctx, C.byref(obs), pb, pm, cap, int(want)), "ising_observables")
+    _check(lib().ising_observables(ctx, C.byref(obs), pb, pm, cap, int(want)), "ising_observables", ctx)
     if bs is not None:
         n = obs.series_len
         bs, ms = bs[:n], ms[:n]
@@ -203,27 +208,28 @@ def ising_observables(ctx, want=0, capacity=None):
 
 def ising_copy_spins(ctx, L):
     out = np.empty((L, L), dtype=np.int8)
-    _check(lib().ising_copy_spins(ctx, out.ctypes.data, out.size), "ising_copy_spins")
+    _check(lib().ising_copy_spins(ctx, out.ctypes.data, out.size), "ising_copy_spins", ctx)
     return out
 
 
 def ising_load_spins(ctx, spins, t):
     a = np.ascontiguousarray(spins, dtype=np.int8)
-    _check(lib().ising_load_spins(ctx, a.ctypes.data, a.size, int(t)), "ising_load_spins")
+    _check(lib().ising_load_spins(ctx, a.ctypes.data, a.size, int(t)), "ising_load_spins", ctx)
 
 
 def ising_sweep_batch(ctxs, n_sweeps, stream=None):
     k = len(ctxs)
     arr = (C.c_void_p * k)(*ctxs)
     ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
-    _check(lib().ising_sweep_batch(arr, ns, k, stream), "ising_sweep_batch")
+    _check(lib().ising_sweep_batch(arr, ns, k, stream), "ising_sweep_batch", ctxs[0] if ctxs else None)
 
 
 def ising_sweep_batch_plan(ctxs, n_sweeps, plan, stream=None):
     k = len(ctxs)
     arr = (C.c_void_p * k)(*ctxs)
     ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
-    _check(lib().ising_sweep_batch_plan(arr, ns, k, stream, int(plan)), "ising_sweep_batch_plan")
+    _check(lib().ising_sweep_batch_plan(arr, ns, k, stream, int(plan)), "ising_sweep_batch_plan",
+           ctxs[0] if ctxs else None)
 
 
 def ising_series_averages(bond, mag, L, J=1.0, h=0.0):
@@ -237,16 +243,16 @@ def ising_series_averages(bond, mag, L, J=1.0, h=0.0):
 
 def ising_plan_info(ctx):
     p, cw, r = C.c_uint32(), C.c_uint32(), C.c_uint32()
-    _check(lib().ising_plan_info(ctx, C.byref(p), C.byref(cw), C.byref(r)), "ising_plan_info")
+    _check(lib().ising_plan_info(ctx, C.byref(p), C.byref(cw), C.byref(r)), "ising_plan_info", ctx)
     return p.value, cw.value, r.value
 
 
 def ising_plan_set(ctx, plan, cw=0, rows=0):
-    _check(lib().ising_plan_set(ctx, int(plan), int(cw), int(rows)), "ising_plan_set")
+    _check(lib().ising_plan_set(ctx, int(plan), int(cw), int(rows)), "ising_plan_set", ctx)
 
 
 def ising_tune(ctx, trial_sweeps=4):
-    _check(lib().ising_tune(ctx, int(trial_sweeps)), "ising_tune")
+    _check(lib().ising_tune(ctx, int(trial_sweeps)), "ising_tune", ctx)
 
 
 def ising_creutz_init(ctx, demons=None, fill=0):
@@ -261,18 +267,18 @@ def ising_creutz_init(ctx, demons=None, fill=0):
 
 
 def ising_creutz_sweep(ctx, n, reverse=False):
-    _check(lib().ising_creutz_sweep(ctx, int(n), 1 if reverse else 0), "ising_creutz_sweep")
+    _check(lib().ising_creutz_sweep(ctx, int(n), 1 if reverse else 0), "ising_creutz_sweep", ctx)
 
 
 def ising_demon_sum(ctx):
     v = C.c_int64()
-    _check(lib().ising_demon_sum(ctx, C.byref(v)), "ising_demon_sum")
+    _check(lib().ising_demon_sum(ctx, C.byref(v)), "ising_demon_sum", ctx)
     return v.value
 
 
 def ising_copy_demons(ctx, L):
     out = np.empty((L, L), dtype=np.uint8)
-    _check(lib().ising_copy_demons(ctx, out.ctypes.data, out.size), "ising_copy_demons")
+    _check(lib().ising_copy_demons(ctx, out.ctypes.data, out.size), "ising_copy_demons", ctx)
     return out
 
 

@@ -32,9 +32,16 @@ struct Engine {
     BatchItem* h_items = nullptr;
     uint32_t* h_order = nullptr;
     BatchHeader* h_hdr = nullptr;
-    hipEvent_t staged = nullptr;  // completion of the last staging copies
+    hipEvent_t staged = nullptr;  // completion of the last staging copies, on the launch stream
     hipEvent_t order_ev = nullptr;
-    hipEvent_t done = nullptr;    // completion of the last launch (any stream)
+    hipEvent_t done = nullptr;    // completion of the last launch, on the launch stream
+    // The launch stream may be a context's stream that is destroyed before
+    // the next call, and an event is only waited on from later calls after
+    // being relayed to the engine's own stream, which lives as long as the
+    // process: these two are the relayed copies.
+    hipStream_t relay = nullptr;
+    hipEvent_t staged_relay = nullptr;
+    hipEvent_t done_relay = nullptr;
     bool staged_pending = false;
     bool launched = false;
     hipGraph_t graph = nullptr;
@@ -90,7 +97,7 @@ void release_buffers(Engine& e) {
 hipError_t ensure_capacity(Engine& e, size_t count) {
     if (count <= e.cap) return hipSuccess;
     if (e.staged_pending) {
-        hipError_t r = hipEventSynchronize(e.staged);
+        hipError_t r = hipEventSynchronize(e.staged_relay);
         if (r != hipSuccess) return r;
         e.staged_pending = false;
     }
@@ -121,6 +128,12 @@ hipError_t init_engine(Engine& e) {
     r = hipEventCreateWithFlags(&e.order_ev, hipEventDisableTiming);
     if (r != hipSuccess) return r;
     r = hipEventCreateWithFlags(&e.done, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    r = hipEventCreateWithFlags(&e.staged_relay, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    r = hipEventCreateWithFlags(&e.done_relay, hipEventDisableTiming);
+    if (r != hipSuccess) return r;
+    r = hipStreamCreateWithFlags(&e.relay, hipStreamNonBlocking);
     if (r != hipSuccess) return r;
     int dev = 0;
     hipDeviceProp_t prop;
@@ -186,11 +199,15 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     hipError_t r = init_engine(e);
     if (r == hipSuccess) r = ensure_capacity(e, count);
     if (r != hipSuccess) {
-        (void)hipGetLastError();
-        return r == hipErrorOutOfMemory ? ISING_ENOMEM : ISING_EDEVICE;
+        if (r == hipErrorOutOfMemory) {
+            (void)hipGetLastError();
+            return ISING_ENOMEM;
+        }
+        return ctx_fail(ctxs[0], r, "engine: set-up");
     }
     if (e.staged_pending) {  // pinned staging area still being read by the last copy
-        if (hipEventSynchronize(e.staged) != hipSuccess) return ISING_EDEVICE;
+        if ((r = hipEventSynchronize(e.staged_relay)) != hipSuccess)
+            return ctx_fail(ctxs[0], r, "engine: staging wait");
         e.staged_pending = false;
     }
     std::vector<uint64_t> work(count);
@@ -246,26 +263,26 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     for (size_t k = 0; k < count; ++k) {
         hipStream_t cs = ctxs[k]->stream;
         if (cs == s) continue;
-        if (hipEventRecord(e.order_ev, cs) != hipSuccess || hipStreamWaitEvent(s, e.order_ev, 0) != hipSuccess)
-            return ctx_fail(ctxs[k], hipErrorUnknown);
+        if ((r = hipEventRecord(e.order_ev, cs)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: record order");
+        if ((r = hipStreamWaitEvent(s, e.order_ev, 0)) != hipSuccess)
+            return ctx_fail(ctxs[k], r, "engine: wait order");
     }
     // the device descriptors may still be read by the previous launch
-    if (e.launched && hipStreamWaitEvent(s, e.done, 0) != hipSuccess) return ctx_fail(ctxs[0], hipErrorUnknown);
-    bool copied;
+    if (e.launched && (r = hipStreamWaitEvent(s, e.done_relay, 0)) != hipSuccess)
+        return ctx_fail(ctxs[0], r, "engine: wait previous launch");
+    r = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s);
     if (!stepped) {
-        copied = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) ==
-                     hipSuccess &&
-                 hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s) ==
-                     hipSuccess &&
-                 hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s) == hipSuccess;
+        if (r == hipSuccess) r = hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        if (r == hipSuccess) r = hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s);
     } else {
-        copied = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s) ==
-                     hipSuccess &&
-                 hipMemcpyAsync(e.d_vbs, e.h_vbs, (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s) ==
-                     hipSuccess &&
-                 hipMemcpyAsync(e.d_mhdr, e.h_mhdr, sizeof(MultiHeader), hipMemcpyHostToDevice, s) == hipSuccess;
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(e.d_vbs, e.h_vbs, (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        if (r == hipSuccess) r = hipMemcpyAsync(e.d_mhdr, e.h_mhdr, sizeof(MultiHeader), hipMemcpyHostToDevice, s);
     }
-    if (!copied || hipEventRecord(e.staged, s) != hipSuccess) return ctx_fail(ctxs[0], hipErrorUnknown);
+    if (r != hipSuccess) return ctx_fail(ctxs[0], r, "engine: stage descriptors");
+    if ((r = hipEventRecord(e.staged, s)) != hipSuccess || (r = hipStreamWaitEvent(e.relay, e.staged, 0)) != hipSuccess ||
+        (r = hipEventRecord(e.staged_relay, e.relay)) != hipSuccess)
+        return ctx_fail(ctxs[0], r, "engine: record staged");
     e.staged_pending = true;
     if (!stepped) {
         r = ensure_graph(e, s);
@@ -275,15 +292,17 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         const uint64_t replays = (max_n + kSweepsPerReplay - 1) / kSweepsPerReplay;
         for (uint64_t k = 0; r == hipSuccess && k < replays; ++k) r = hipGraphLaunch(e.mexec, s);
     }
-    if (r == hipSuccess) r = hipEventRecord(e.done, s);
-    if (r != hipSuccess) return ctx_fail(ctxs[0], r);
+    if (r != hipSuccess) return ctx_fail(ctxs[0], r, stepped ? "engine: stepped graph" : "engine: resident graph");
+    if ((r = hipEventRecord(e.done, s)) != hipSuccess || (r = hipStreamWaitEvent(e.relay, e.done, 0)) != hipSuccess ||
+        (r = hipEventRecord(e.done_relay, e.relay)) != hipSuccess)
+        return ctx_fail(ctxs[0], r, "engine: record done");
     e.launched = true;
     // and every context's later work after it
     for (size_t k = 0; k < count; ++k) {
         hipStream_t cs = ctxs[k]->stream;
         if (cs == s) continue;
-        if (hipEventRecord(e.order_ev, s) != hipSuccess || hipStreamWaitEvent(cs, e.order_ev, 0) != hipSuccess)
-            return ctx_fail(ctxs[k], hipErrorUnknown);
+        if ((r = hipEventRecord(e.order_ev, s)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: record after");
+        if ((r = hipStreamWaitEvent(cs, e.order_ev, 0)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: wait after");
     }
     for (size_t k = 0; k < count; ++k) {
         ctxs[k]->t += n[k];

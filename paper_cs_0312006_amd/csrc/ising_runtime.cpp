@@ -2,6 +2,8 @@
 // The public contract (model, keying, error behaviour) is in include/ising.h.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -166,23 +168,26 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
 // ---------------------------------------------------------------------------
 // Context helpers
 // ---------------------------------------------------------------------------
-int ctx_fail(ising_ctx* ctx, hipError_t e) {
+int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where) {
     ctx->poisoned = true;
     ctx->last_hip = e;
+    std::snprintf(ctx->device_error, sizeof(ctx->device_error), "%.100s: %s (%d)", where ? where : "",
+                  hipGetErrorName(e), (int)e);
+    (void)hipGetLastError();
     return ISING_EDEVICE;
 }
 
-#define HIP_TRY(ctx, expr)                       \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return ctx_fail((ctx), e_); \
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return ctx_fail((ctx), e_, #expr); \
     } while (0)
 
 static int ctx_enter(ising_ctx* ctx) {
     if (!ctx) return ISING_EINVAL;
     if (ctx->poisoned) return ISING_ESTATE;
     hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return ctx_fail(ctx, e);
+    if (e != hipSuccess) return ctx_fail(ctx, e, "hipSetDevice");
     return ISING_OK;
 }
 
@@ -666,7 +671,7 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     ising_destroy(tmp);
-    if (rc != ISING_OK) return rc == ISING_EDEVICE ? ctx_fail(ctx, hipErrorUnknown) : rc;
+    if (rc != ISING_OK) return rc == ISING_EDEVICE ? ctx_fail(ctx, hipErrorUnknown, "autotuner trial context") : rc;
     const Plan old = ctx->plan;
     ctx->plan = best;
     rc = ctx_prepare_plan(ctx);
@@ -784,6 +789,10 @@ int ising_destroy(ising_ctx* ctx) {
     (void)hipGetLastError();
     delete ctx;
     return ISING_OK;
+}
+
+const char* ising_device_error(const ising_ctx* ctx) {
+    return ctx ? ctx->device_error : "";
 }
 
 const char* ising_strerror(int code) {

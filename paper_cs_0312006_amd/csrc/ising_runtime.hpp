@@ -50,13 +50,15 @@ struct ising_ctx {
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;
     hipError_t last_hip = hipSuccess;
+    char device_error[160] = {0};  // failing call and HIP error of the last EDEVICE
 };
 
 ising::Planes ctx_planes(const ising_ctx* ctx);
 ising::Planes ctx_planes_alt(const ising_ctx* ctx);
 int ctx_reserve_series(ising_ctx* ctx, uint64_t more);
 int ctx_prepare_plan(ising_ctx* ctx);
-int ctx_fail(ising_ctx* ctx, hipError_t e);
+// Poison the context after a failed HIP call `where` and return EDEVICE.
+int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 
 // Batch engine (ising_engine.cpp): run ctxs[k] for n[k] sweeps each on
 // stream s, either as one persistent workgroup-resident launch or as the
