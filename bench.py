@@ -26,14 +26,15 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit ops)
 
 # Figures measured with rocprofv3 for the fused kernel as built from these
-# sources (profiles/k_fused_ising2d_32768.md). They are reported only while
-# the kernel sources hash to the recorded value; otherwise they are null.
+# sources (profiles/k_fused_ising2d_32768.md), per tile shape. They are
+# reported only while the kernel sources hash to the recorded value and the
+# timed plan is one of these; otherwise they are null.
+PROFILED_SOURCES = "9169ba37a72ee186"
 PROFILED = {
-    "sources_sha256_16": "8ab160f9dd0d74c3",
-    "kernel": "k_fused<4,32>",
-    "hbm_bytes_per_launch": 1393929.0 * 1024 + 1048847.0 * 1024,  # FETCH x2.0 + WRITE x1.0
-    "valu_lane_ops_per_attempt": 16.54,
-    "valu_busy_rocprof": 0.96,
+    # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch, mean of 54)
+    "k_fused<4,32>": {"hbm_bytes_per_launch": (698114.6 * 2.0 + 1048845.5) * 1024,
+                      "valu_lane_ops_per_attempt": 277456490.4 * 64 / 2 ** 30,
+                      "valu_busy_rocprof": 0.971},
 }
 
 
@@ -63,7 +64,7 @@ def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None):
         if force:
             b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, force[0], force[1])
         elif tune:
-            b.ising_tune(ctx, 4)
+            b.ising_tune(ctx, 8)
         plan = b.ising_plan_info(ctx)
         if warmup:
             b.ising_sweep(ctx, warmup)
@@ -340,6 +341,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--epoch-sweeps", type=int, default=64)
     ap.add_argument("--creutz-sweeps", type=int, default=100)
+    ap.add_argument("--only", choices=["creutz", "percolation", "micro"], default=None,
+                    help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -355,6 +358,16 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.Stream()
 
+    if args.only:
+        if args.only == "creutz":
+            leg = run_creutz(b, torch, stream, args.creutz_sweeps, float("nan"))
+        elif args.only == "percolation":
+            leg = run_percolation(b, cpu=False)
+        else:
+            leg = run_micro(b, torch, stream)
+        print(json.dumps({"leg": args.only, "result": leg}), flush=True)
+        return
+
     run = W.C2_HEADLINE
     force = (args.cw, args.rows) if (args.cw or args.rows) else None
     head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force)
@@ -368,19 +381,20 @@ def main():
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
 
     kname = f"k_fused<{plan[1]},{plan[2]}>" if plan[0] == 2 else "k_two_pass"
-    same_kernel = kernel_sources_hash() == PROFILED["sources_sha256_16"] and kname == PROFILED["kernel"]
-    traffic = PROFILED["hbm_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 if same_kernel else None
+    prof = PROFILED.get(kname) if kernel_sources_hash() == PROFILED_SOURCES else None
+    same_kernel = prof is not None
+    traffic = prof["hbm_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 if same_kernel else None
     roof_hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": launch_ms}
     roof_alu = None
     if same_kernel:
-        ops = PROFILED["valu_lane_ops_per_attempt"] * run.L * run.L / (launch_ms * 1e-3)
+        ops = prof["valu_lane_ops_per_attempt"] * run.L * run.L / (launch_ms * 1e-3)
         roof_alu = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
                     "unit": "T lane-ops/s (32-bit VALU)", "frac": ops / VALU_PEAK_LANE_OPS, "traffic": traffic,
                     "traffic_unit": "GB/s", "kernel": kname,
-                    "ops_per_attempt": PROFILED["valu_lane_ops_per_attempt"],
-                    "valu_busy_rocprof": PROFILED["valu_busy_rocprof"], "avg_launch_ms": launch_ms}
+                    "ops_per_attempt": prof["valu_lane_ops_per_attempt"],
+                    "valu_busy_rocprof": prof["valu_busy_rocprof"], "avg_launch_ms": launch_ms}
     out = {
         "metric": "spin-update attempts/ns",
         "value": value,

@@ -200,9 +200,11 @@ int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
 
 /* Autotuner: time `trial_sweeps` sweeps of every plan and fused tile shape
  * that can serve the context's L on a scratch copy of its lattice (the
- * context's own state is untouched), switch the context to the fastest and
- * remember it for later AUTO contexts of the same L in this process.
- * Synchronises. The chosen plan is readable with ising_plan_info. */
+ * context's own state is untouched), in three interleaved rounds keeping
+ * each candidate's fastest; switch the context to the fastest (the default
+ * plan for L stays unless another is more than 3% faster) and remember it
+ * for later AUTO contexts of the same L in this process. Synchronises. The
+ * chosen plan is readable with ising_plan_info. */
 int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps);
 
 /* ---- Creutz demon dynamics (Section 2.2) --------------------------------

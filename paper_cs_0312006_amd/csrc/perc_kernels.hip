@@ -8,10 +8,13 @@
 // relaxation, arrival = min(arrival, 1 + min over the four neighbours), in
 // 64 x 64 tiles held in LDS: a workgroup relaxes its tile to a local fixed
 // point (many steps per HBM round trip), and a tile is revisited only when
-// a neighbouring tile changed the sites on their shared edge. Values only
-// ever decrease and every read value is an upper bound of the true
-// distance, so the unique fixed point, reached when no tile is queued, is
-// exact whatever the timing of concurrent reads.
+// a neighbouring tile changed the sites on their shared edge. Launch k
+// admits arrival values up to 64 (k + 1) only (larger improvements wait in
+// their tile, which stays queued), so the front is swept roughly in
+// breadth-first order and tiles are seldom recomputed. Values only ever
+// decrease and every read value is an upper bound of the true distance, so
+// the unique fixed point, reached when no tile is queued, is exact
+// whatever the timing of concurrent reads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +27,7 @@ namespace {
 
 constexpr uint32_t kSide = kTile + 2;          // tile plus one-site halo
 constexpr uint32_t kMaxIters = 1u << 14;       // per visit; a tile still changing is queued again
+constexpr uint32_t kBoundStep = 64;            // arrival passes admitted per launch
 
 // LDS accesses of the relaxation: other waves update neighbouring rows
 // concurrently, so reads and writes are relaxed atomics (plain ds_read /
@@ -37,11 +41,17 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v) {
 
 // New arrival of a site from its current value and its four neighbours
 // (solid neighbours hold 0xffffffff, unreached ones kUnreached, and both
-// give kUnreached + 1 > any reachable value).
-__device__ __forceinline__ uint32_t relax1(uint32_t cur, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+// give kUnreached + 1 > any reachable value). Improvements beyond this
+// launch's bound are left for a later launch and flagged as pending.
+__device__ __forceinline__ uint32_t relax1(uint32_t cur, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
+                                           uint32_t bound, bool& pend) {
     uint32_t m = min(min(a, b), min(c, d));
     m = min(m, kUnreached) + 1u;
-    return min(cur, m);
+    if (m < cur) {
+        if (m <= bound) return m;
+        pend = true;
+    }
+    return cur;
 }
 
 __device__ __forceinline__ void push(const WorkLists& w, uint32_t par, uint32_t lout, uint32_t tile) {
@@ -108,7 +118,7 @@ __global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, uint32_t n_
 // whose shared edge changed.
 __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty,
                                                          WorkLists w, uint32_t pin, uint32_t lin, uint32_t lout,
-                                                         uint32_t lclr, Stats* st) {
+                                                         uint32_t lclr, uint32_t bound, Stats* st) {
     __shared__ uint32_t d[kSide * kSide];
     if (blockIdx.x == 0 && threadIdx.x == 0) w.len[lclr] = 0u;
     const uint32_t n = w.len[lin];
@@ -138,8 +148,10 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
         uint32_t* col = d + x + 1;  // this thread's column; row yy at col[yy * kSide]
         uint32_t iters = 0;
         int go;
+        bool pend;
         do {
             bool ch = false;
+            pend = false;
             // top to bottom along the strip, then bottom to top
             uint32_t up = lds_ld(col + y0 * kSide);
             uint32_t cur = lds_ld(col + (y0 + 1) * kSide);
@@ -148,7 +160,8 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
                 const uint32_t yy = y0 + 1 + r;
                 const uint32_t dn = lds_ld(col + (yy + 1) * kSide);
                 if (cur != kSolid) {
-                    const uint32_t nv = relax1(cur, up, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1));
+                    const uint32_t nv = relax1(cur, up, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1),
+                                                    bound, pend);
                     if (nv < cur) {
                         lds_st(col + yy * kSide, nv);
                         cur = nv;
@@ -165,7 +178,8 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
                 const uint32_t yy = y0 + kStrip - r;
                 const uint32_t upv = lds_ld(col + (yy - 1) * kSide);
                 if (cur != kSolid) {
-                    const uint32_t nv = relax1(cur, upv, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1));
+                    const uint32_t nv = relax1(cur, upv, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1),
+                                                    bound, pend);
                     if (nv < cur) {
                         lds_st(col + yy * kSide, nv);
                         cur = nv;
@@ -184,7 +198,8 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
                 for (uint32_t c = 1; c <= kStrip; ++c) {
                     const uint32_t rt = lds_ld(row + c + 1);
                     if (c2 != kSolid) {
-                        const uint32_t nv = relax1(c2, lf, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide));
+                        const uint32_t nv = relax1(c2, lf, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide), bound,
+                                                        pend);
                         if (nv < c2) {
                             lds_st(row + c, nv);
                             c2 = nv;
@@ -200,7 +215,8 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
                 for (uint32_t c = kStrip; c >= 1; --c) {
                     const uint32_t lv = lds_ld(row + c - 1);
                     if (c2 != kSolid) {
-                        const uint32_t nv = relax1(c2, lv, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide));
+                        const uint32_t nv = relax1(c2, lv, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide), bound,
+                                                        pend);
                         if (nv < c2) {
                             lds_st(row + c, nv);
                             c2 = nv;
@@ -214,6 +230,9 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
             ++iters;
             go = __syncthreads_or(ch);
         } while (go && iters < kMaxIters);
+        // pending improvements of the last (unchanging) iteration: revisit
+        // the tile in the next launch, whose bound is higher
+        const int later = __syncthreads_or(pend);
         if (threadIdx.x == 0) {
             atomicAdd(&st->visits, 1ull);
             atomicAdd(&st->iterations, (unsigned long long)iters);
@@ -241,7 +260,7 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
             if (bot && ty + 1 < n_ty) push(w, par, lout, tile + n_tx);
             if (lft && tx > 0) push(w, par, lout, tile - 1);
             if (rgt && tx + 1 < n_tx) push(w, par, lout, tile + 1);
-            if (go) push(w, par, lout, tile);  // visit cap reached: not yet at its fixed point
+            if (go || later) push(w, par, lout, tile);  // not yet at its fixed point
         }
     }
 }
@@ -296,8 +315,13 @@ hipError_t launch_seed_lists(const WorkLists& w, uint32_t n_tx, uint32_t n_tiles
 
 hipError_t launch_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty, const WorkLists& w, uint64_t k,
                         uint32_t grid, Stats* stats, hipStream_t s) {
+    // arrival passes accepted in launch k: up to (k + 1) * kBoundStep, so the
+    // invasion front is swept in order, a band per launch, and tiles are
+    // rarely revisited with a better value
+    const uint64_t b = (k + 1) * (uint64_t)kBoundStep;
+    const uint32_t bound = b >= kUnreached ? kUnreached - 1 : (uint32_t)b;
     k_perc_relax<<<grid, kThreads, 0, s>>>(arr, L, n_tx, n_ty, w, (uint32_t)(k % 2), (uint32_t)(k % 3),
-                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3), stats);
+                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3), bound, stats);
     return hipGetLastError();
 }
 
