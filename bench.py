@@ -35,6 +35,10 @@ PROFILED = {
     "k_fused<4,32>": {"hbm_bytes_per_launch": (698114.6 * 2.0 + 1048845.5) * 1024,
                       "valu_lane_ops_per_attempt": 277456490.4 * 64 / 2 ** 30,
                       "valu_busy_rocprof": 0.971},
+    # mean of 52
+    "k_fused<4,16>": {"hbm_bytes_per_launch": (745646.1 * 2.0 + 1049109.3) * 1024,
+                      "valu_lane_ops_per_attempt": 289885138.0 * 64 / 2 ** 30,
+                      "valu_busy_rocprof": 0.993},
 }
 
 
@@ -165,7 +169,61 @@ def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
                                      "value": sub_attempts / ms_solo / 1e6,
                                      "results_identical_to_batched": bool(same)}
     res["speedup_vs_one_launch_per_lattice"] = (total / ms) / (sub_attempts / ms_solo)
+    # the same sample on 8 streams (each lattice on its own context stream,
+    # calls issued round-robin, then all synchronised): labelled comparator
+    streams = [torch.cuda.Stream() for _ in range(8)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=streams[k % 8].cuda_stream)
+            for k, r in enumerate(sub)]
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, r in zip(ctxs, sub):
+            b.ising_sweep(c, r.sweeps)
+        torch.cuda.synchronize()
+        ms_multi = (time.perf_counter() - t0) * 1e3
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
+    res["one_launch_per_lattice_8_streams"] = {"lattices": len(sub), "ms": ms_multi,
+                                               "value": sub_attempts / ms_multi / 1e6,
+                                               "clock": "host, around issue and final synchronise"}
     return res, hashes
+
+
+def run_small_configs(b, torch, stream):
+    """The 64^2 config (1000 sweeps) and the three 4096^2 configs (2000
+    sweeps each): throughput over the whole run with the autotuned plan, and
+    p50/p99 latency of 10-sweep calls (enqueue to result on the host, one
+    call at a time)."""
+    import numpy as np
+    from paper_cs_0312006_amd import workloads as W
+    out = []
+    for run in [W.C0] + list(W.C1):
+        ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
+        try:
+            b.ising_tune(ctx, 10)
+            plan = b.ising_plan_info(ctx)
+            b.ising_observables(ctx, b.ISING_OBS_SERIES)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.ising_sweep(ctx, run.sweeps)
+            b.ising_observables(ctx, b.ISING_OBS_SERIES)
+            whole = time.perf_counter() - t0
+            lat = []
+            for _ in range(200):
+                t1 = time.perf_counter()
+                b.ising_sweep(ctx, 10)
+                b.ising_observables(ctx, b.ISING_OBS_SERIES)
+                lat.append(time.perf_counter() - t1)
+        finally:
+            b.ising_destroy(ctx)
+        lat = np.array(lat)
+        out.append({"workload": f"ising2d {run.L}x{run.L} T={run.T} seed {run.seed}, {run.sweeps} sweeps",
+                    "plan": {"kind": plan[0], "chunk_words": plan[1], "tile_rows": plan[2]},
+                    "value": run.attempts() / whole / 1e9, "unit": "attempts/ns (host clock, incl. series copy)",
+                    "s": whole, "chunk10_p50_us": float(np.percentile(lat, 50) * 1e6),
+                    "chunk10_p99_us": float(np.percentile(lat, 99) * 1e6)})
+    return out
 
 
 def run_served(rates, count, epoch_sweeps):
@@ -337,7 +395,9 @@ def main():
     ap.add_argument("--batched-sweeps", type=int, default=10000)
     ap.add_argument("--batched-sample", type=int, default=64)
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-rates", type=str, default="100,1000,5000")
+    ap.add_argument("--served-rates", type=str, default="100,200,500,1000,2000,5000")
+    ap.add_argument("--served-subsat-rate", type=float, default=10.0,
+                    help="one extra, sub-saturation arrival rate (0: skip)")
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--epoch-sweeps", type=int, default=64)
     ap.add_argument("--creutz-sweeps", type=int, default=100)
@@ -441,6 +501,14 @@ def main():
 
     if not args.no_extra and not args.no_served:
         out["served"] = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
+        if args.served_subsat_rate > 0:
+            sub = run_served(str(args.served_subsat_rate), args.served_requests, args.epoch_sweeps)
+            for x in sub:
+                x["label"] = "sub-saturation point (extra, not a configured rate)"
+            out["served_subsaturation"] = sub
+
+    if not args.no_extra:
+        out["small_configs"] = run_small_configs(b, torch, stream)
 
     if not args.no_extra:
         out["creutz"] = run_creutz(b, torch, stream, args.creutz_sweeps, value)

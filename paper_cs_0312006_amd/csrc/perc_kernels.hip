@@ -152,79 +152,61 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
         do {
             bool ch = false;
             pend = false;
-            // top to bottom along the strip, then bottom to top
-            uint32_t up = lds_ld(col + y0 * kSide);
-            uint32_t cur = lds_ld(col + (y0 + 1) * kSide);
-#pragma unroll
-            for (uint32_t r = 0; r < kStrip; ++r) {
-                const uint32_t yy = y0 + 1 + r;
-                const uint32_t dn = lds_ld(col + (yy + 1) * kSide);
-                if (cur != kSolid) {
-                    const uint32_t nv = relax1(cur, up, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1),
-                                                    bound, pend);
-                    if (nv < cur) {
-                        lds_st(col + yy * kSide, nv);
-                        cur = nv;
-                        ch = true;
-                    }
-                }
-                up = cur;
-                cur = dn;
-            }
-            uint32_t dn = lds_ld(col + (y0 + kStrip + 1) * kSide);
-            cur = lds_ld(col + (y0 + kStrip) * kSide);
-#pragma unroll
-            for (uint32_t r = 0; r < kStrip; ++r) {
-                const uint32_t yy = y0 + kStrip - r;
-                const uint32_t upv = lds_ld(col + (yy - 1) * kSide);
-                if (cur != kSolid) {
-                    const uint32_t nv = relax1(cur, upv, dn, lds_ld(col + yy * kSide - 1), lds_ld(col + yy * kSide + 1),
-                                                    bound, pend);
-                    if (nv < cur) {
-                        lds_st(col + yy * kSide, nv);
-                        cur = nv;
-                        ch = true;
-                    }
-                }
-                dn = cur;
-                cur = upv;
-            }
-            // left to right along a 16-site row segment, then right to left
             {
-                uint32_t* row = d + (hr + 1) * kSide + hx0;  // row[c] = site column hx0 + c - 1
-                uint32_t lf = lds_ld(row);
-                uint32_t c2 = lds_ld(row + 1);
+                // column strip: LDS rows y0 .. y0 + 17 of column x, own sites
+                // 1 .. 16; all reads issued first, the chain then runs in
+                // registers, top to bottom and back
+                uint32_t c[kStrip + 2], lf[kStrip], rt[kStrip], o[kStrip];
 #pragma unroll
-                for (uint32_t c = 1; c <= kStrip; ++c) {
-                    const uint32_t rt = lds_ld(row + c + 1);
-                    if (c2 != kSolid) {
-                        const uint32_t nv = relax1(c2, lf, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide), bound,
-                                                        pend);
-                        if (nv < c2) {
-                            lds_st(row + c, nv);
-                            c2 = nv;
-                            ch = true;
-                        }
-                    }
-                    lf = c2;
-                    c2 = rt;
+                for (uint32_t r = 0; r < kStrip + 2; ++r) c[r] = lds_ld(col + (y0 + r) * kSide);
+#pragma unroll
+                for (uint32_t r = 0; r < kStrip; ++r) {
+                    lf[r] = lds_ld(col + (y0 + 1 + r) * kSide - 1);
+                    rt[r] = lds_ld(col + (y0 + 1 + r) * kSide + 1);
+                    o[r] = c[r + 1];
                 }
-                uint32_t rt = lds_ld(row + kStrip + 1);
-                c2 = lds_ld(row + kStrip);
 #pragma unroll
-                for (uint32_t c = kStrip; c >= 1; --c) {
-                    const uint32_t lv = lds_ld(row + c - 1);
-                    if (c2 != kSolid) {
-                        const uint32_t nv = relax1(c2, lv, rt, lds_ld(row + c - kSide), lds_ld(row + c + kSide), bound,
-                                                        pend);
-                        if (nv < c2) {
-                            lds_st(row + c, nv);
-                            c2 = nv;
-                            ch = true;
-                        }
+                for (uint32_t r = 1; r <= kStrip; ++r)
+                    if (c[r] != kSolid) c[r] = relax1(c[r], c[r - 1], c[r + 1], lf[r - 1], rt[r - 1], bound, pend);
+#pragma unroll
+                for (uint32_t r = kStrip; r >= 1; --r)
+                    if (c[r] != kSolid) c[r] = relax1(c[r], c[r - 1], c[r + 1], lf[r - 1], rt[r - 1], bound, pend);
+#pragma unroll
+                for (uint32_t r = 0; r < kStrip; ++r) {
+                    if (c[r + 1] != o[r]) {
+                        lds_st(col + (y0 + 1 + r) * kSide, c[r + 1]);
+                        ch = true;
                     }
-                    rt = c2;
-                    c2 = lv;
+                }
+            }
+            // each site has one writer per phase: its column owner above,
+            // its row owner below, so a site's value never goes up
+            __syncthreads();
+            {
+                // row segment: LDS columns hx0 .. hx0 + 17 of row hr + 1, own
+                // sites 1 .. 16, left to right and back
+                uint32_t* row = d + (hr + 1) * kSide + hx0;
+                uint32_t c[kStrip + 2], up[kStrip], dn[kStrip], o[kStrip];
+#pragma unroll
+                for (uint32_t k = 0; k < kStrip + 2; ++k) c[k] = lds_ld(row + k);
+#pragma unroll
+                for (uint32_t k = 0; k < kStrip; ++k) {
+                    up[k] = lds_ld(row + k + 1 - kSide);
+                    dn[k] = lds_ld(row + k + 1 + kSide);
+                    o[k] = c[k + 1];
+                }
+#pragma unroll
+                for (uint32_t k = 1; k <= kStrip; ++k)
+                    if (c[k] != kSolid) c[k] = relax1(c[k], c[k - 1], c[k + 1], up[k - 1], dn[k - 1], bound, pend);
+#pragma unroll
+                for (uint32_t k = kStrip; k >= 1; --k)
+                    if (c[k] != kSolid) c[k] = relax1(c[k], c[k - 1], c[k + 1], up[k - 1], dn[k - 1], bound, pend);
+#pragma unroll
+                for (uint32_t k = 0; k < kStrip; ++k) {
+                    if (c[k + 1] != o[k]) {
+                        lds_st(row + k + 1, c[k + 1]);
+                        ch = true;
+                    }
                 }
             }
             ++iters;
