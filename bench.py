@@ -310,6 +310,28 @@ def run_percolation(b, cpu=True):
                         "value": N * max(1, r.passes) / s / 1e9,
                         "unit": "site-passes/ns (one full pass per invasion step, as in Section 2.3)"}})
     res = {"runs": out}
+    # the spanning threshold (Section 2.3): per-seed porosity from which the
+    # medium spans, by bisection (14 halvings of [0.3, 0.9]), for 64 media of
+    # the paper's Figure 3 size
+    import numpy as np
+    t0 = time.perf_counter()
+    th = []
+    for seed in range(64):
+        lo, hi = 0.3, 0.9
+        for _ in range(14):
+            mid = 0.5 * (lo + hi)
+            ctx = b.perc_create(512, mid, 1000 + seed)
+            try:
+                b.perc_run(ctx)
+                sp = b.perc_result_get(ctx).spans & 1
+            finally:
+                b.perc_destroy(ctx)
+            lo, hi = (lo, mid) if sp else (mid, hi)
+        th.append(hi)
+    th = np.array(th)
+    res["spanning_threshold_512"] = {"media": len(th), "median": float(np.median(th)), "mean": float(th.mean()),
+                                     "sd": float(th.std(ddof=1)), "s": time.perf_counter() - t0,
+                                     "reference_p_c": 0.592746}
     if cpu:
         from oracle import ref
         o = ref.Oracle()

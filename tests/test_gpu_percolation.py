@@ -103,3 +103,29 @@ def test_full_size_medium_and_arrival(b):
     spans = (1 if inv[0].any() and inv[-1].any() else 0) | (2 if inv[:, 0].any() and inv[:, -1].any() else 0)
     assert (r.pores, r.invaded, r.passes, r.spans) == (int(pore.sum(dtype=np.int64)), int(inv.sum()),
                                                       int(arr.max()), spans)
+
+
+def _span_threshold_gpu(b, L, seed, lo=0.3, hi=0.9, iters=14):
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        ctx = b.perc_create(L, mid, seed)
+        try:
+            b.perc_run(ctx)
+            sp = b.perc_result_get(ctx).spans & 1
+        finally:
+            b.perc_destroy(ctx)
+        lo, hi = (lo, mid) if sp else (mid, hi)
+    return hi
+
+
+def test_spanning_thresholds_equal_oracle(b, o):
+    """Section 2.3's question, the porosity from which a spanning cluster
+    exists: per-seed spanning thresholds of 128 x 128 media found by
+    bisection on the GPU equal the oracle's exactly, and their median lies
+    near p_c = 0.592746."""
+    from tests.test_oracle_percolation import _span_threshold
+    G.log("spanning thresholds, 40 media of 128^2")
+    gpu = [_span_threshold_gpu(b, 128, s) for s in range(40)]
+    cpu = [_span_threshold(o, 128, s) for s in range(40)]
+    assert gpu == cpu
+    assert abs(float(np.median(gpu)) - 0.592746) < 0.012
