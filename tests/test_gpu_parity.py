@@ -251,3 +251,19 @@ def test_c2_32768_sampled(b, o, k):
     G.log(f"C2 window checks h={run.h} p_up={run.p_up}")
     checked = _check_windows(o, run, g["spins"], run.sweeps, corners)
     assert checked >= 2 * 16 * 16
+
+
+@pytest.mark.parametrize("L,sweeps", [(65536, 12), (65534, 3)])
+def test_largest_sides(b, o, L, sweeps):
+    """The largest side the ABI accepts (65536: fused plan, 4 GiB planes) and
+    the largest side that is not a multiple of 8 (65534: per-site kernel):
+    invariants every sweep, the last (B, M) equal to the oracle's
+    observables of the whole final lattice, and two light-cone windows (one
+    wrapping the periodic corner) exact against the oracle."""
+    run = W.Run(L=L, h=0.1, T=2.269185, seed=5, p_up=0.5, sweeps=sweeps)
+    G.log(f"largest side L={L} {sweeps} sweeps")
+    g = G.gpu_run(b, run)
+    _check_invariants(g["B"], g["M"], L)
+    assert (int(g["B"][-1]), int(g["M"][-1])) == o.observables(g["spins"])
+    corners = [(L - 20, L - 30), (L // 3, 2 * L // 3)]
+    assert _check_windows(o, run, g["spins"], sweeps, corners) >= 2 * 16 * 16
