@@ -467,7 +467,8 @@ def main():
     same_kernel = prof is not None
     traffic = prof["hbm_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 if same_kernel else None
     roof_hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kname,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "traffic_frac": traffic / HBM_PEAK_GBS if traffic else None, "kernel": kname,
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": launch_ms}
     roof_alu = None
     if same_kernel:
