@@ -271,28 +271,30 @@ __global__ void __launch_bounds__(256) k_observe(Planes pl, int64_t* out) {
 // ---------------------------------------------------------------------------
 // Layout conversion between planes and canonical row-major int8 +1 / -1.
 // ---------------------------------------------------------------------------
+// Grid-stride over the L*L sites (a 65536^2 lattice has 2^32 sites, more
+// than one launch can give a thread each).
 __global__ void __launch_bounds__(256) k_to_canonical(Planes pl, int8_t* out) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t N = (size_t)pl.L * pl.L;
-    if (idx >= N) return;
-    const uint32_t i = (uint32_t)(idx / pl.L), j = (uint32_t)(idx - (size_t)i * pl.L);
-    const uint32_t c = (i + j) & 1u;
-    out[idx] = pl.p[c][(size_t)i * pl.H + (j >> 1)] ? (int8_t)1 : (int8_t)-1;
+    const size_t N = (size_t)pl.L * pl.L, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+        const uint32_t i = (uint32_t)(idx / pl.L), j = (uint32_t)(idx - (size_t)i * pl.L);
+        const uint32_t c = (i + j) & 1u;
+        out[idx] = pl.p[c][(size_t)i * pl.H + (j >> 1)] ? (int8_t)1 : (int8_t)-1;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_from_canonical(Planes pl, const int8_t* in) {
-    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const size_t N = (size_t)pl.L * pl.L;
-    if (idx >= N) return;
-    const uint32_t i = (uint32_t)(idx / pl.L), j = (uint32_t)(idx - (size_t)i * pl.L);
-    const uint32_t c = (i + j) & 1u;
-    pl.p[c][(size_t)i * pl.H + (j >> 1)] = in[idx] > 0 ? 1u : 0u;
+    const size_t N = (size_t)pl.L * pl.L, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < N; idx += stride) {
+        const uint32_t i = (uint32_t)(idx / pl.L), j = (uint32_t)(idx - (size_t)i * pl.L);
+        const uint32_t c = (i + j) & 1u;
+        pl.p[c][(size_t)i * pl.H + (j >> 1)] = in[idx] > 0 ? 1u : 0u;
+    }
 }
 
 // Fill n int64 with zero (a kernel, not a memset, so it can sit in a graph).
 __global__ void __launch_bounds__(256) k_zero_i64(int64_t* p, uint64_t n) {
-    const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < n) p[idx] = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) p[idx] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -362,17 +364,20 @@ hipError_t launch_observe(const Planes& pl, int64_t* out, hipStream_t s) {
 
 hipError_t launch_zero(int64_t* p, uint64_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    k_zero_i64<<<blocks_for(n, 256), 256, 0, s>>>(p, n);
+    const uint32_t nb = blocks_for(n, 256);
+    k_zero_i64<<<nb > 4096u ? 4096u : (nb ? nb : 1u), 256, 0, s>>>(p, n);
     return hipGetLastError();
 }
 
 hipError_t launch_to_canonical(const Planes& pl, int8_t* out, hipStream_t s) {
-    k_to_canonical<<<blocks_for((uint64_t)pl.L * pl.L, 256), 256, 0, s>>>(pl, out);
+    const uint32_t nb = blocks_for((uint64_t)pl.L * pl.L, 256);
+    k_to_canonical<<<nb > 65536u ? 65536u : nb, 256, 0, s>>>(pl, out);
     return hipGetLastError();
 }
 
 hipError_t launch_from_canonical(const Planes& pl, const int8_t* in, hipStream_t s) {
-    k_from_canonical<<<blocks_for((uint64_t)pl.L * pl.L, 256), 256, 0, s>>>(pl, in);
+    const uint32_t nb = blocks_for((uint64_t)pl.L * pl.L, 256);
+    k_from_canonical<<<nb > 65536u ? 65536u : nb, 256, 0, s>>>(pl, in);
     return hipGetLastError();
 }
 
