@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ising_creutz.hpp"
 #include "ising_device.hpp"
 #include "ising_launch.hpp"
 
@@ -18,25 +19,6 @@ namespace ising {
 namespace {
 
 constexpr uint32_t kCreutzThreads = 256;
-
-// Demon update of four sites at once. W: spin bytes (0/1), n: up-neighbour
-// counts (0..4), D: demon bytes. With g = e + 2 = (s ? n : 4 - n) in 0..4,
-// y = d + 258 - g lies in [254, 513] and the move is allowed iff
-// 256 <= y <= 511, in which case the new demon is y - 256. Even and odd
-// bytes are handled in 16-bit lanes so y never borrows across sites.
-__device__ __forceinline__ void creutz_word(uint32_t W, uint32_t n, uint32_t D, uint32_t& Wn, uint32_t& Dn) {
-    const uint32_t sm = W * 0xffu;
-    const uint32_t g = (n & sm) | ((0x04040404u - n) & ~sm);
-    const uint32_t ye = (D & 0x00ff00ffu) + 0x01020102u - (g & 0x00ff00ffu);
-    const uint32_t yo = ((D >> 8) & 0x00ff00ffu) + 0x01020102u - ((g >> 8) & 0x00ff00ffu);
-    const uint32_t fe = (ye >> 8) & ~(ye >> 9) & 0x00010001u;
-    const uint32_t fo = (yo >> 8) & ~(yo >> 9) & 0x00010001u;
-    const uint32_t f = fe | (fo << 8);
-    const uint32_t fm = f * 0xffu;
-    const uint32_t y = (ye & 0x00ff00ffu) | ((yo & 0x00ff00ffu) << 8);
-    Wn = W ^ f;
-    Dn = (y & fm) | (D & ~fm);
-}
 
 }  // namespace
 

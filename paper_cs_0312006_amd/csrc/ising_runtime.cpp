@@ -16,6 +16,7 @@
 
 #include "ising.h"
 #include "ising_launch.hpp"
+#include "ising_creutz.hpp"
 #include "ising_runtime.hpp"
 
 using namespace ising;
@@ -727,6 +728,67 @@ int ising_creutz_init(ising_ctx* ctx, const uint8_t* host, size_t n, uint8_t fil
     return ISING_OK;
 }
 
+// Buffers of the fused Creutz sweep: the second spin and demon buffers
+// (ping-pong) and per-tile partials for the (cw, rows) tiling.
+static int creutz_fused_prepare(ising_ctx* ctx, uint32_t cw, uint32_t rows) {
+    const size_t N = (size_t)ctx->L * ctx->L;
+    if (!ctx->buf[1]) {
+        if (hipMalloc(&ctx->buf[1], N) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->buf[1] = nullptr;
+            return ISING_ENOMEM;
+        }
+        ctx->owns_buf[1] = true;
+    }
+    if (!ctx->demon_alt) {
+        if (hipMalloc(&ctx->demon_alt, N) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->demon_alt = nullptr;
+            return ISING_ENOMEM;
+        }
+    }
+    const uint32_t need = fused_tiles(ctx->L, cw, rows);
+    if (need > ctx->cfpart_cap) {
+        for (int k = 0; k < 2; ++k) {
+            if (ctx->cfpart[k]) (void)hipFree(ctx->cfpart[k]);
+            ctx->cfpart[k] = nullptr;
+        }
+        ctx->cfpart_cap = 0;
+        for (int k = 0; k < 2; ++k) {
+            if (hipMalloc(&ctx->cfpart[k], (size_t)need * 2 * sizeof(int64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
+            }
+        }
+        ctx->cfpart_cap = need;
+    }
+    return ISING_OK;
+}
+
+// n fused Creutz sweeps; series slots ser[0 .. 2n).
+static int creutz_sweep_fused(ising_ctx* ctx, uint64_t n, uint32_t cw, uint32_t rows, int64_t* ser) {
+    const uint32_t L = ctx->L, Hw = L / 8u;
+    const uint32_t n_tx = Hw / (64u * cw);
+    const uint32_t n_tiles = fused_tiles(L, cw, rows);
+    for (uint64_t k = 0; k < n; ++k) {
+        const Planes src = ctx_planes(ctx), dst = ctx_planes_alt(ctx);
+        const Planes ds = planes_of(ctx->demon, L), dd = planes_of(ctx->demon_alt, L);
+        CreutzFusedArgs a{reinterpret_cast<const uint32_t*>(src.p[0]), reinterpret_cast<const uint32_t*>(src.p[1]),
+                          reinterpret_cast<const uint32_t*>(ds.p[0]), reinterpret_cast<const uint32_t*>(ds.p[1]),
+                          reinterpret_cast<uint32_t*>(dst.p[0]), reinterpret_cast<uint32_t*>(dst.p[1]),
+                          reinterpret_cast<uint32_t*>(dd.p[0]), reinterpret_cast<uint32_t*>(dd.p[1]),
+                          L, Hw, n_tx, n_tiles, ctx->cfpart[k & 1]};
+        PartialReduce red{nullptr, 0, nullptr};
+        if (k > 0) red = PartialReduce{ctx->cfpart[(k - 1) & 1], n_tiles, ser + 2 * (k - 1)};
+        HIP_TRY(ctx, launch_creutz_fused(a, cw, rows, red, ctx->stream));
+        ctx->cur ^= 1;
+        std::swap(ctx->demon, ctx->demon_alt);
+    }
+    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->cfpart[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)},
+                                        ctx->stream));
+    return ISING_OK;
+}
+
 int ising_creutz_sweep(ising_ctx* ctx, uint64_t n, int reverse) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;
@@ -735,6 +797,15 @@ int ising_creutz_sweep(ising_ctx* ctx, uint64_t n, int reverse) {
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
     int64_t* ser = ctx->series + 2 * ctx->series_len;
+    uint32_t cw = 0, rows = 0;
+    if (!reverse && ctx->L % 8u == 0u && default_fused(ctx->L, &cw, &rows)) {
+        rc = creutz_fused_prepare(ctx, cw, rows);
+        if (rc != ISING_OK) return rc;
+        rc = creutz_sweep_fused(ctx, n, cw, rows, ser);
+        if (rc != ISING_OK) return rc;
+        ctx->series_len += n;
+        return ISING_OK;
+    }
     const Planes pl = ctx_planes(ctx), dm = planes_of(ctx->demon, ctx->L);
     if (ctx->L % 8u == 0u) {
         const uint32_t nb = creutz_blocks(pl);
@@ -792,7 +863,10 @@ int ising_destroy(ising_ctx* ctx) {
     }
     if (ctx->series) (void)hipFree(ctx->series);
     if (ctx->demon) (void)hipFree(ctx->demon);
+    if (ctx->demon_alt) (void)hipFree(ctx->demon_alt);
     if (ctx->cpart) (void)hipFree(ctx->cpart);
+    for (int k = 0; k < 2; ++k)
+        if (ctx->cfpart[k]) (void)hipFree(ctx->cfpart[k]);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->canon) (void)hipFree(ctx->canon);
     if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);

@@ -46,7 +46,10 @@ struct ising_ctx {
     int64_t* scratch = nullptr;  // 4 int64 for observables
     int8_t* canon = nullptr;     // N bytes, canonical layout staging
     uint8_t* demon = nullptr;    // Creutz demons (N bytes, colour-plane layout), once initialised
+    uint8_t* demon_alt = nullptr;  // second demon buffer for the fused (ping-pong) Creutz sweep
     int64_t* cpart = nullptr;    // Creutz per-block (B, M) partials
+    int64_t* cfpart[2] = {nullptr, nullptr};  // fused Creutz per-tile partials, double-buffered
+    uint32_t cfpart_cap = 0;
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;
     hipError_t last_hip = hipSuccess;
