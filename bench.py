@@ -42,13 +42,23 @@ PROFILED = {
 }
 
 
-def kernel_sources_hash():
+# Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md),
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch, mean of 22
+PROFILED_CREUTZ_SOURCES = "9125b02e811f5446"
+PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
+                   "hbm_bytes_per_sweep": (1316787.4 * 2.0 + 2097588.4) * 1024}
+
+
+def kernel_sources_hash(files=("ising_fused.hip", "ising_device.hpp", "ising_launch.hpp")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("ising_fused.hip", "ising_device.hpp", "ising_launch.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_cs_0312006_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+CREUTZ_FILES = ("ising_creutz_fused.hip", "ising_creutz.hpp", "ising_device.hpp", "ising_launch.hpp")
 
 
 def host_cores():
@@ -272,6 +282,8 @@ def run_creutz(b, torch, stream, sweeps, metropolis_value):
     N = run.L * run.L
     value = N * sweeps / ms / 1e6
     achieved = 4.0 * N / (ms / sweeps * 1e-3) / 1e9
+    same = kernel_sources_hash(CREUTZ_FILES) == PROFILED_CREUTZ_SOURCES
+    traffic = PROFILED_CREUTZ["hbm_bytes_per_sweep"] / (ms / sweeps * 1e-3) / 1e9 if same else None
     t_demon = 4.0 / __import__("math").log1p(N / demons) if demons else None
     return {"workload": f"creutz demons {run.L}x{run.L}, hot start seed {run.seed}, demons 0",
             "sweeps": sweeps, "value": value, "unit": "site updates/ns", "ms_per_sweep": ms / sweeps,
@@ -279,8 +291,8 @@ def run_creutz(b, torch, stream, sweeps, metropolis_value):
             "energy_conserved": bool(-obs.bond_sum + 4 * demons == -obs0.bond_sum),
             "demon_temperature": t_demon,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                         "kernel": "k_creutz_words (two passes per sweep)",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                         "kernel": PROFILED_CREUTZ["kernel"] + " (one launch per sweep)",
                          "algorithmic_bytes_per_sweep": 4.0 * N}}
 
 

@@ -132,3 +132,7 @@ def test_percolation_rejects_bad_parameters(b):
         with pytest.raises(b.IsingError) as e:
             b.perc_create(**kw)
         assert e.value.code == b.ISING_EINVAL
+
+
+def test_device_error_of_null_context_is_empty(b):
+    assert b.lib().ising_device_error(None) == b""
