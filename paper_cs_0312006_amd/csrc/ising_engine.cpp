@@ -26,6 +26,9 @@ struct Engine {
     std::mutex mu;
     bool ready = false;
     size_t cap = 0;
+    uint8_t* d_stage = nullptr;  // staging block on the device and its pinned host mirror
+    uint8_t* h_stage = nullptr;
+    size_t off_items = 0;
     BatchItem* d_items = nullptr;
     uint32_t* d_order = nullptr;
     BatchHeader* d_hdr = nullptr;
@@ -71,26 +74,20 @@ void release_buffers(Engine& e) {
     if (e.mgraph) (void)hipGraphDestroy(e.mgraph);
     e.mexec = nullptr;
     e.mgraph = nullptr;
-    if (e.d_vbs) (void)hipFree(e.d_vbs);
-    if (e.h_vbs) (void)hipHostFree(e.h_vbs);
-    if (e.d_mhdr) (void)hipFree(e.d_mhdr);
-    if (e.h_mhdr) (void)hipHostFree(e.h_mhdr);
-    e.d_vbs = nullptr;
-    e.h_vbs = nullptr;
-    e.d_mhdr = nullptr;
-    e.h_mhdr = nullptr;
-    if (e.d_items) (void)hipFree(e.d_items);
-    if (e.d_order) (void)hipFree(e.d_order);
-    if (e.d_hdr) (void)hipFree(e.d_hdr);
-    if (e.h_items) (void)hipHostFree(e.h_items);
-    if (e.h_order) (void)hipHostFree(e.h_order);
-    if (e.h_hdr) (void)hipHostFree(e.h_hdr);
+    if (e.d_stage) (void)hipFree(e.d_stage);
+    if (e.h_stage) (void)hipHostFree(e.h_stage);
+    e.d_stage = nullptr;
+    e.h_stage = nullptr;
     e.d_items = nullptr;
     e.d_order = nullptr;
     e.d_hdr = nullptr;
     e.h_items = nullptr;
     e.h_order = nullptr;
     e.h_hdr = nullptr;
+    e.d_vbs = nullptr;
+    e.h_vbs = nullptr;
+    e.d_mhdr = nullptr;
+    e.h_mhdr = nullptr;
     e.cap = 0;
 }
 
@@ -107,16 +104,25 @@ hipError_t ensure_capacity(Engine& e, size_t count) {
     release_buffers(e);
     size_t cap = 256;
     while (cap < count) cap *= 2;
-    if ((r = hipMalloc(&e.d_items, cap * sizeof(BatchItem))) != hipSuccess) return r;
-    if ((r = hipMalloc(&e.d_order, cap * sizeof(uint32_t))) != hipSuccess) return r;
-    if ((r = hipMalloc(&e.d_hdr, sizeof(BatchHeader))) != hipSuccess) return r;
-    if ((r = hipHostMalloc(&e.h_items, cap * sizeof(BatchItem), hipHostMallocDefault)) != hipSuccess) return r;
-    if ((r = hipHostMalloc(&e.h_order, cap * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) return r;
-    if ((r = hipHostMalloc(&e.h_hdr, sizeof(BatchHeader), hipHostMallocDefault)) != hipSuccess) return r;
-    if ((r = hipMalloc(&e.d_vbs, (cap + 1) * sizeof(uint32_t))) != hipSuccess) return r;
-    if ((r = hipHostMalloc(&e.h_vbs, (cap + 1) * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) return r;
-    if ((r = hipMalloc(&e.d_mhdr, sizeof(MultiHeader))) != hipSuccess) return r;
-    if ((r = hipHostMalloc(&e.h_mhdr, sizeof(MultiHeader), hipHostMallocDefault)) != hipSuccess) return r;
+    // one staging block, [hdr | mhdr | order | vbs | items], so that a call
+    // stages its descriptors with a single copy
+    const size_t off_order = 64;
+    const size_t off_vbs = off_order + cap * sizeof(uint32_t);
+    const size_t off_items = (off_vbs + (cap + 1) * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t bytes = off_items + cap * sizeof(BatchItem);
+    if ((r = hipMalloc(&e.d_stage, bytes)) != hipSuccess) return r;
+    if ((r = hipHostMalloc(&e.h_stage, bytes, hipHostMallocDefault)) != hipSuccess) return r;
+    e.off_items = off_items;
+    e.d_hdr = reinterpret_cast<BatchHeader*>(e.d_stage);
+    e.d_mhdr = reinterpret_cast<MultiHeader*>(e.d_stage + 32);
+    e.d_order = reinterpret_cast<uint32_t*>(e.d_stage + off_order);
+    e.d_vbs = reinterpret_cast<uint32_t*>(e.d_stage + off_vbs);
+    e.d_items = reinterpret_cast<BatchItem*>(e.d_stage + off_items);
+    e.h_hdr = reinterpret_cast<BatchHeader*>(e.h_stage);
+    e.h_mhdr = reinterpret_cast<MultiHeader*>(e.h_stage + 32);
+    e.h_order = reinterpret_cast<uint32_t*>(e.h_stage + off_order);
+    e.h_vbs = reinterpret_cast<uint32_t*>(e.h_stage + off_vbs);
+    e.h_items = reinterpret_cast<BatchItem*>(e.h_stage + off_items);
     e.cap = cap;
     return hipSuccess;
 }
@@ -270,15 +276,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     // the device descriptors may still be read by the previous launch
     if (e.launched && (r = hipStreamWaitEvent(s, e.done_relay, 0)) != hipSuccess)
         return ctx_fail(ctxs[0], r, "engine: wait previous launch");
-    r = hipMemcpyAsync(e.d_items, e.h_items, count * sizeof(BatchItem), hipMemcpyHostToDevice, s);
-    if (!stepped) {
-        if (r == hipSuccess) r = hipMemcpyAsync(e.d_order, e.h_order, count * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-        if (r == hipSuccess) r = hipMemcpyAsync(e.d_hdr, e.h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, s);
-    } else {
-        if (r == hipSuccess)
-            r = hipMemcpyAsync(e.d_vbs, e.h_vbs, (count + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
-        if (r == hipSuccess) r = hipMemcpyAsync(e.d_mhdr, e.h_mhdr, sizeof(MultiHeader), hipMemcpyHostToDevice, s);
-    }
+    r = hipMemcpyAsync(e.d_stage, e.h_stage, e.off_items + count * sizeof(BatchItem), hipMemcpyHostToDevice, s);
     if (r != hipSuccess) return ctx_fail(ctxs[0], r, "engine: stage descriptors");
     if ((r = hipEventRecord(e.staged, s)) != hipSuccess || (r = hipStreamWaitEvent(e.relay, e.staged, 0)) != hipSuccess ||
         (r = hipEventRecord(e.staged_relay, e.relay)) != hipSuccess)

@@ -501,11 +501,10 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
     if (want & ~(ISING_OBS_HASH | ISING_OBS_SERIES)) return ISING_EINVAL;
     const uint64_t len = ctx->series_len;
     if ((want & ISING_OBS_SERIES) && (bond_series || mag_series) && capacity < len) return ISING_ERANGE;
-    HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
     int64_t bm[2] = {0, 0};
-    HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->scratch, sizeof(bm), hipMemcpyDeviceToHost, ctx->stream));
     std::vector<int64_t> ser;
-    if ((want & ISING_OBS_SERIES) && len && (bond_series || mag_series)) {
+    const bool copy_series = (want & ISING_OBS_SERIES) && len && (bond_series || mag_series);
+    if (copy_series) {
         try {
             ser.resize(2 * len);
         } catch (...) {
@@ -513,6 +512,13 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
         }
         HIP_TRY(ctx, hipMemcpyAsync(ser.data(), ctx->series, 2 * len * sizeof(int64_t), hipMemcpyDeviceToHost,
                                     ctx->stream));
+    } else if (len) {
+        // the last series entry is the current lattice's (B, M)
+        HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->series + 2 * (len - 1), sizeof(bm), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    } else {
+        HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->scratch, sizeof(bm), hipMemcpyDeviceToHost, ctx->stream));
     }
     uint64_t hsh = 0;
     if (want & ISING_OBS_HASH) {
@@ -532,8 +538,10 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
     } else {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     }
-    if (want & ISING_OBS_SERIES) {
-        for (uint64_t k = 0; k < len && !ser.empty(); ++k) {
+    if (copy_series) {
+        bm[0] = ser[2 * (len - 1)];
+        bm[1] = ser[2 * (len - 1) + 1];
+        for (uint64_t k = 0; k < len; ++k) {
             if (bond_series) bond_series[k] = ser[2 * k];
             if (mag_series) mag_series[k] = ser[2 * k + 1];
         }
