@@ -27,7 +27,10 @@ namespace {
 
 constexpr uint32_t kSide = kTile + 2;          // tile plus one-site halo
 constexpr uint32_t kMaxIters = 1u << 14;       // per visit; a tile still changing is queued again
-constexpr uint32_t kBoundStep = 64;            // arrival passes admitted per launch
+#ifndef PERC_BOUND_STEP
+#define PERC_BOUND_STEP 64
+#endif
+constexpr uint32_t kBoundStep = PERC_BOUND_STEP;  // arrival passes admitted per launch
 
 // LDS accesses of the relaxation: other waves update neighbouring rows
 // concurrently, so reads and writes are relaxed atomics (plain ds_read /
