@@ -254,7 +254,7 @@ def run_served(rates, count, epoch_sweeps):
     return out
 
 
-def run_creutz(b, torch, stream, sweeps, metropolis_value):
+def run_creutz(b, torch, stream, sweeps, metropolis_value, cpu=True):
     """Creutz demon sweeps of the 32768^2 hot start with empty demons
     (Section 2.2's random-number-free alternative), timed like the headline;
     algorithmic traffic 4 B per site and sweep (spin and demon bytes, each
@@ -285,7 +285,26 @@ def run_creutz(b, torch, stream, sweeps, metropolis_value):
     same = kernel_sources_hash(CREUTZ_FILES) == PROFILED_CREUTZ_SOURCES
     traffic = PROFILED_CREUTZ["hbm_bytes_per_sweep"] / (ms / sweeps * 1e-3) / 1e9 if same else None
     t_demon = 4.0 / __import__("math").log1p(N / demons) if demons else None
+    res_cpu = None
+    if cpu:
+        # the oracle's Creutz sweeps on a 16384^2 sample of the same start
+        import numpy as np
+        from oracle import ref
+        o = ref.Oracle()
+        cores = min(16, host_cores())
+        o.set_threads(cores)
+        Ls, n_cpu = 16384, 4
+        s_ = o.init(Ls, run.seed, run.p_up)
+        d_ = np.zeros((Ls, Ls), dtype=np.uint8)
+        t0 = time.perf_counter()
+        o.creutz_run(s_, d_, n_cpu, series=False)
+        dt = time.perf_counter() - t0
+        res_cpu = {"value": Ls * Ls * n_cpu / dt / 1e9, "unit": "site updates/ns", "cores": cores,
+                   "kind": "oracle", "sample": f"{n_cpu} Creutz sweeps of a {Ls}x{Ls} hot start (seed {run.seed}), "
+                                               f"empty demons, {dt:.2f} s"}
+        del s_, d_
     return {"workload": f"creutz demons {run.L}x{run.L}, hot start seed {run.seed}, demons 0",
+            "cpu_baseline": res_cpu,
             "sweeps": sweeps, "value": value, "unit": "site updates/ns", "ms_per_sweep": ms / sweeps,
             "vs_metropolis_headline": value / metropolis_value,
             "energy_conserved": bool(-obs.bond_sum + 4 * demons == -obs0.bond_sum),
@@ -412,7 +431,10 @@ def run_micro(b, torch, stream):
             tr.append({"op": name, "lattice": side, "bytes": nbytes, "s": ms * 1e-3, "MB_per_s": nbytes / ms / 1e3})
         del host, dev
     copy_gbs = max(v["GB_per_s"] for v in vec if v["op"] == "=" and v["lattice"] == 8192)
-    return {"vector_ops": vec, "transfers": tr, "achievable_hbm_copy_GB_per_s": copy_gbs}
+    return {"vector_ops": vec, "transfers": tr, "achievable_hbm_copy_GB_per_s": copy_gbs,
+            "roofline": {"bound": "hbm", "achieved": copy_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": copy_gbs / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_vec<copy>, 1 GiB float vector (8 bytes moved per float)"}}
 
 
 def main():
@@ -454,7 +476,7 @@ def main():
 
     if args.only:
         if args.only == "creutz":
-            leg = run_creutz(b, torch, stream, args.creutz_sweeps, float("nan"))
+            leg = run_creutz(b, torch, stream, args.creutz_sweeps, float("nan"), cpu=False)
         elif args.only == "percolation":
             leg = run_percolation(b, cpu=False)
         else:
@@ -546,7 +568,7 @@ def main():
         out["small_configs"] = run_small_configs(b, torch, stream)
 
     if not args.no_extra:
-        out["creutz"] = run_creutz(b, torch, stream, args.creutz_sweeps, value)
+        out["creutz"] = run_creutz(b, torch, stream, args.creutz_sweeps, value, cpu=not args.no_cpu)
         out["percolation"] = run_percolation(b, cpu=not args.no_cpu)
         out["micro"] = run_micro(b, torch, stream)
 

@@ -9,7 +9,7 @@
 // 64 x 64 tiles held in LDS: a workgroup relaxes its tile to a local fixed
 // point (many steps per HBM round trip), and a tile is revisited only when
 // a neighbouring tile changed the sites on their shared edge. Launch k
-// admits arrival values up to 64 (k + 1) only (larger improvements wait in
+// admits arrival values up to 32 (k + 1) only (larger improvements wait in
 // their tile, which stays queued), so the front is swept roughly in
 // breadth-first order and tiles are seldom recomputed. Values only ever
 // decrease and every read value is an upper bound of the true distance, so
@@ -28,7 +28,7 @@ namespace {
 constexpr uint32_t kSide = kTile + 2;          // tile plus one-site halo
 constexpr uint32_t kMaxIters = 1u << 14;       // per visit; a tile still changing is queued again
 #ifndef PERC_BOUND_STEP
-#define PERC_BOUND_STEP 64
+#define PERC_BOUND_STEP 32
 #endif
 constexpr uint32_t kBoundStep = PERC_BOUND_STEP;  // arrival passes admitted per launch
 
