@@ -343,26 +343,42 @@ def run_percolation(b, cpu=True):
     res = {"runs": out}
     # the spanning threshold (Section 2.3): per-seed porosity from which the
     # medium spans, by bisection (14 halvings of [0.3, 0.9]), for 64 media of
-    # the paper's Figure 3 size
+    # the paper's Figure 3 size: all media in one batched run per step, and
+    # (comparator) one medium at a time
     import numpy as np
-    t0 = time.perf_counter()
-    th = []
-    for seed in range(64):
-        lo, hi = 0.3, 0.9
-        for _ in range(14):
+    n_media, side, steps = 64, 512, 14
+    ctxs = [b.perc_create(side, 0.5, 1000 + k) for k in range(n_media)]
+    try:
+        b.perc_run_batch(ctxs)  # warm
+        t0 = time.perf_counter()
+        lo, hi = np.full(n_media, 0.3), np.full(n_media, 0.9)
+        for _ in range(steps):
             mid = 0.5 * (lo + hi)
-            ctx = b.perc_create(512, mid, 1000 + seed)
-            try:
-                b.perc_run(ctx)
-                sp = b.perc_result_get(ctx).spans & 1
-            finally:
-                b.perc_destroy(ctx)
-            lo, hi = (lo, mid) if sp else (mid, hi)
-        th.append(hi)
-    th = np.array(th)
-    res["spanning_threshold_512"] = {"media": len(th), "median": float(np.median(th)), "mean": float(th.mean()),
-                                     "sd": float(th.std(ddof=1)), "s": time.perf_counter() - t0,
-                                     "reference_p_c": 0.592746}
+            for k, c in enumerate(ctxs):
+                b.perc_set_params(c, side, float(mid[k]), 1000 + k)
+            b.perc_run_batch(ctxs)
+            sp = np.array([b.perc_result_get(c).spans & 1 for c in ctxs], dtype=bool)
+            hi = np.where(sp, mid, hi)
+            lo = np.where(sp, lo, mid)
+        t_batch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        th_one = []
+        for k, c in enumerate(ctxs):
+            a, z = 0.3, 0.9
+            for _ in range(steps):
+                m = 0.5 * (a + z)
+                b.perc_set_params(c, side, m, 1000 + k)
+                b.perc_run(c)
+                a, z = (a, m) if b.perc_result_get(c).spans & 1 else (m, z)
+            th_one.append(z)
+        t_one = time.perf_counter() - t0
+    finally:
+        for c in ctxs:
+            b.perc_destroy(c)
+    res["spanning_threshold_512"] = {"media": n_media, "median": float(np.median(hi)), "mean": float(hi.mean()),
+                                     "sd": float(hi.std(ddof=1)), "reference_p_c": 0.592746,
+                                     "s_batched": t_batch, "s_one_medium_at_a_time": t_one,
+                                     "same_thresholds": bool(list(hi) == th_one)}
     if cpu:
         from oracle import ref
         o = ref.Oracle()

@@ -157,14 +157,18 @@ int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n);
  * pending series. Synchronises. */
 int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
 
-/* Run n_sweeps[k] sweeps on ctxs[k], k < count, as one persistent launch
- * (plus a small reset launch) on `stream` (NULL: the first context's
- * stream): each workgroup takes whole lattices, largest work first, and
- * runs all of their sweeps. Lattices may differ in L, J, h, T and seed;
- * each must satisfy L % 8 == 0 and have no pending device error. Contexts
- * are validated before anything is launched (all-or-nothing). The results
- * are bit-identical to calling ising_sweep on each context alone.
- * Asynchronous; the contexts' own streams are ordered after it. */
+/* Run n_sweeps[k] sweeps on ctxs[k], k < count, together on `stream`
+ * (NULL: the first context's stream), with the batch plan ISING_BATCH_AUTO
+ * picks (see ising_sweep_batch_plan): one persistent launch from a captured
+ * graph in which each workgroup takes whole lattices, largest work first,
+ * and runs all of their sweeps, or, when some side is above 256, graph
+ * replays of passes that spread every lattice over the whole GPU. The
+ * descriptors are staged with one host-to-device copy. Lattices may differ
+ * in L, J, h, T and seed; each must satisfy L % 8 == 0 and have no pending
+ * device error. Contexts are validated before anything is launched
+ * (all-or-nothing). The results are bit-identical to calling ising_sweep on
+ * each context alone. Asynchronous; the contexts' own streams are ordered
+ * after it. */
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream);
 
 /* As ising_sweep_batch with an explicit batch plan:

@@ -69,6 +69,21 @@ int perc_create(const perc_params* params, void* stream, perc_ctx** out);
  * ESTATE, EDEVICE. */
 int perc_run(perc_ctx* ctx);
 
+/* Draw and invade the media of `count` contexts together, with the same
+ * results as perc_run on each: every relaxation launch covers the queued
+ * tiles of all of them, so many small media fill the GPU (Section 2.3 asks
+ * for the porosity from which a spanning cluster exists, a question over
+ * many media). Runs on the first context's stream after each context's
+ * earlier work. Synchronises. Errors: EINVAL (NULL or repeated contexts,
+ * contexts on different devices), ESTATE, ERANGE (more than 2^32 tiles
+ * together), ENOMEM, EDEVICE (the first context is poisoned). */
+int perc_run_batch(perc_ctx* const* ctxs, size_t count);
+
+/* Change the porosity, seed and invasion source of a context for its next
+ * run; params->L must equal the context's side (the buffers are kept).
+ * Errors: EINVAL (invalid params or another side), ESTATE. */
+int perc_set_params(perc_ctx* ctx, const perc_params* params);
+
 /* Summary of the last run into *out; want_hash != 0 also hashes the arrival
  * map (copies it to the host). Errors: EINVAL, ESTATE (no run yet). */
 int perc_result_get(perc_ctx* ctx, perc_result* out, uint32_t want_hash);

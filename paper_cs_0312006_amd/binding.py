@@ -106,6 +106,8 @@ SIGNATURES = {
     "perc_copy_medium": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "perc_copy_arrival": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "perc_destroy": (C.c_int, [C.c_void_p]),
+    "perc_run_batch": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t]),
+    "perc_set_params": (C.c_int, [C.c_void_p, C.POINTER(perc_params)]),
     "mb_vector_op": (C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mb_copy_lattice": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                   C.c_void_p]),
@@ -295,6 +297,17 @@ def perc_create(L, porosity, seed=0, source=PERC_SOURCE_TOP_ROW, i0=0, j0=0, str
 
 def perc_run(ctx):
     _check(lib().perc_run(ctx), "perc_run")
+
+
+def perc_run_batch(ctxs):
+    k = len(ctxs)
+    arr = (C.c_void_p * k)(*ctxs)
+    _check(lib().perc_run_batch(arr, k), "perc_run_batch")
+
+
+def perc_set_params(ctx, L, porosity, seed=0, source=PERC_SOURCE_TOP_ROW, i0=0, j0=0):
+    p = perc_params(int(L), float(porosity), int(seed), int(source), int(i0), int(j0))
+    _check(lib().perc_set_params(ctx, C.byref(p)), "perc_set_params")
 
 
 def perc_result_get(ctx, want_hash=False):

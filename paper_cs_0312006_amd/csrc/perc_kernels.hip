@@ -57,11 +57,11 @@ __device__ __forceinline__ uint32_t relax1(uint32_t cur, uint32_t a, uint32_t b,
     return cur;
 }
 
-__device__ __forceinline__ void push(const WorkLists& w, uint32_t par, uint32_t lout, uint32_t tile) {
-    uint32_t* q = w.queued[par];
-    if (atomicExch(&q[tile], 1u) == 0u) {
+__device__ __forceinline__ void push(const WorkLists& w, uint32_t* queued, uint32_t par, uint32_t lout, uint32_t m,
+                                     uint32_t tile) {
+    if (atomicExch(&queued[tile], 1u) == 0u) {
         const uint32_t pos = atomicAdd(&w.len[lout], 1u);
-        w.list[par][pos] = tile;
+        w.list[par][pos] = make_uint2(m, tile);
     }
 }
 
@@ -94,34 +94,31 @@ __global__ void __launch_bounds__(kThreads) k_perc_draw(uint8_t* pore, uint32_t*
     if ((threadIdx.x & 63u) == 0u && s) atomicAdd(&st->pores, (unsigned long long)s);
 }
 
-// Initial work list: the tiles holding the source, and cleared counters.
-__global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, uint32_t n_tx, uint32_t source, uint32_t i0,
-                                                        uint32_t j0) {
-    uint32_t* q = w.queued[0];
+__global__ void k_perc_reset(WorkLists w) {
+    if (threadIdx.x < 3) w.len[threadIdx.x] = 0u;
+}
+
+// Medium m's source tiles, appended to work list 0.
+__global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, const Medium* media, uint32_t m, uint32_t n_tx,
+                                                        uint32_t source, uint32_t i0, uint32_t j0) {
+    uint32_t* q = media[m].queued[0];
     if (source == 0u) {
         for (uint32_t t = threadIdx.x; t < n_tx; t += blockDim.x) {
-            w.list[0][t] = t;
             q[t] = 1u;
+            w.list[0][atomicAdd(&w.len[0], 1u)] = make_uint2(m, t);
         }
-        if (threadIdx.x == 0) w.len[0] = n_tx;
     } else if (threadIdx.x == 0) {
         const uint32_t t = (i0 / kTile) * n_tx + j0 / kTile;
-        w.list[0][0] = t;
         q[t] = 1u;
-        w.len[0] = 1u;
-    }
-    if (threadIdx.x == 0) {
-        w.len[1] = 0u;
-        w.len[2] = 0u;
+        w.list[0][atomicAdd(&w.len[0], 1u)] = make_uint2(m, t);
     }
 }
 
 // One relaxation launch (number k of the run): relax every listed tile to
 // its local fixed point, write back what changed, queue the neighbours
 // whose shared edge changed.
-__global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty,
-                                                         WorkLists w, uint32_t pin, uint32_t lin, uint32_t lout,
-                                                         uint32_t lclr, uint32_t bound, Stats* st) {
+__global__ void __launch_bounds__(kThreads) k_perc_relax(const Medium* __restrict__ media, WorkLists w, uint32_t pin,
+                                                         uint32_t lin, uint32_t lout, uint32_t lclr, uint32_t bound) {
     __shared__ uint32_t d[kSide * kSide];
     if (blockIdx.x == 0 && threadIdx.x == 0) w.len[lclr] = 0u;
     const uint32_t n = w.len[lin];
@@ -131,9 +128,13 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
     // one column segment; the 66-word row pitch spreads them over banks)
     const uint32_t hr = threadIdx.x & (kTile - 1);
     const uint32_t hx0 = (threadIdx.x / kTile) * kStrip;
-    uint32_t* q_in = w.queued[pin];
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
-        const uint32_t tile = w.list[pin][e];
+        const uint2 ent = w.list[pin][e];
+        const uint32_t m = ent.x, tile = ent.y;
+        const Medium md = media[m];
+        uint32_t* const arr = md.arr;
+        const uint32_t L = md.L, n_tx = md.n_tx, n_ty = md.n_ty;
+        uint32_t* q_in = md.queued[pin];
         const uint32_t ty = tile / n_tx, tx = tile - ty * n_tx;
         const int64_t gi0 = (int64_t)ty * kTile - 1, gj0 = (int64_t)tx * kTile - 1;  // halo origin
         if (threadIdx.x == 0) q_in[tile] = 0u;
@@ -219,8 +220,8 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
         // the tile in the next launch, whose bound is higher
         const int later = __syncthreads_or(pend);
         if (threadIdx.x == 0) {
-            atomicAdd(&st->visits, 1ull);
-            atomicAdd(&st->iterations, (unsigned long long)iters);
+            atomicAdd(&md.stats->visits, 1ull);
+            atomicAdd(&md.stats->iterations, (unsigned long long)iters);
         }
         bool top = false, bot = false, lft = false, rgt = false;
 #pragma unroll
@@ -241,11 +242,12 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(uint32_t* arr, uint32_t
         rgt = __syncthreads_or(rgt);
         if (threadIdx.x == 0) {
             const uint32_t par = pin ^ 1u;
-            if (top && ty > 0) push(w, par, lout, tile - n_tx);
-            if (bot && ty + 1 < n_ty) push(w, par, lout, tile + n_tx);
-            if (lft && tx > 0) push(w, par, lout, tile - 1);
-            if (rgt && tx + 1 < n_tx) push(w, par, lout, tile + 1);
-            if (go || later) push(w, par, lout, tile);  // not yet at its fixed point
+            uint32_t* q_out = md.queued[par];
+            if (top && ty > 0) push(w, q_out, par, lout, m, tile - n_tx);
+            if (bot && ty + 1 < n_ty) push(w, q_out, par, lout, m, tile + n_tx);
+            if (lft && tx > 0) push(w, q_out, par, lout, m, tile - 1);
+            if (rgt && tx + 1 < n_tx) push(w, q_out, par, lout, m, tile + 1);
+            if (go || later) push(w, q_out, par, lout, m, tile);  // not yet at its fixed point
         }
     }
 }
@@ -291,22 +293,25 @@ hipError_t launch_draw(uint8_t* pore, uint32_t* arr, uint32_t L, uint64_t pthr, 
     return hipGetLastError();
 }
 
-hipError_t launch_seed_lists(const WorkLists& w, uint32_t n_tx, uint32_t n_tiles, uint32_t source, uint32_t i0,
-                             uint32_t j0, hipStream_t s) {
-    (void)n_tiles;
-    k_perc_seed<<<1, kThreads, 0, s>>>(w, n_tx, source, i0, j0);
+hipError_t launch_reset_lists(const WorkLists& w, hipStream_t s) {
+    k_perc_reset<<<1, 64, 0, s>>>(w);
     return hipGetLastError();
 }
 
-hipError_t launch_relax(uint32_t* arr, uint32_t L, uint32_t n_tx, uint32_t n_ty, const WorkLists& w, uint64_t k,
-                        uint32_t grid, Stats* stats, hipStream_t s) {
+hipError_t launch_seed(const WorkLists& w, const Medium* media, uint32_t m, uint32_t n_tx, uint32_t source,
+                       uint32_t i0, uint32_t j0, hipStream_t s) {
+    k_perc_seed<<<1, kThreads, 0, s>>>(w, media, m, n_tx, source, i0, j0);
+    return hipGetLastError();
+}
+
+hipError_t launch_relax(const Medium* media, const WorkLists& w, uint64_t k, uint32_t grid, hipStream_t s) {
     // arrival passes accepted in launch k: up to (k + 1) * kBoundStep, so the
     // invasion front is swept in order, a band per launch, and tiles are
     // rarely revisited with a better value
     const uint64_t b = (k + 1) * (uint64_t)kBoundStep;
     const uint32_t bound = b >= kUnreached ? kUnreached - 1 : (uint32_t)b;
-    k_perc_relax<<<grid, kThreads, 0, s>>>(arr, L, n_tx, n_ty, w, (uint32_t)(k % 2), (uint32_t)(k % 3),
-                                           (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3), bound, stats);
+    k_perc_relax<<<grid, kThreads, 0, s>>>(media, w, (uint32_t)(k % 2), (uint32_t)(k % 3), (uint32_t)((k + 1) % 3),
+                                           (uint32_t)((k + 2) % 3), bound);
     return hipGetLastError();
 }
 

@@ -129,3 +129,74 @@ def test_spanning_thresholds_equal_oracle(b, o):
     cpu = [_span_threshold(o, 128, s) for s in range(40)]
     assert gpu == cpu
     assert abs(float(np.median(gpu)) - 0.592746) < 0.012
+
+
+BATCH = [W.Medium(1, 0.5, 21), W.Medium(7, 0.6, 22), W.Medium(64, 0.5927, 23), W.Medium(65, 0.65, 24, 1, 32, 40),
+         W.Medium(130, 1.0, 25), W.Medium(257, 0.6, 26), W.Medium(512, 0.55, 27, 1, 500, 3),
+         W.Medium(200, 0.0, 28), W.Medium(512, 0.6, 29)]
+
+
+def test_batch_equals_oracle_and_single_runs(b, o):
+    """Nine media of mixed sides, porosities and sources in one batched run:
+    each arrival map equals the oracle's and each summary the one of the
+    same medium run alone."""
+    G.log("percolation batch of 9 media")
+    ctxs = [b.perc_create(m.L, m.porosity, m.seed, m.source, m.i0, m.j0) for m in BATCH]
+    try:
+        b.perc_run_batch(ctxs)
+        got = [(b.perc_result_get(c, True), b.perc_copy_arrival(c, m.L)) for c, m in zip(ctxs, BATCH)]
+    finally:
+        for c in ctxs:
+            b.perc_destroy(c)
+    for (r, arr), m in zip(got, BATCH):
+        arr_o = o.perc_invade(o.perc_medium(m.L, m.porosity, m.seed), m.source, m.i0, m.j0)
+        assert np.array_equal(arr, arr_o), f"{m}: arrival differs"
+        solo, _, _ = _gpu(b, m)
+        assert (r.arrival_hash, r.invaded, r.passes, r.spans, r.pores) == (
+            solo.arrival_hash, solo.invaded, solo.passes, solo.spans, solo.pores)
+
+
+def test_set_params_and_batch_errors(b, o):
+    ctx = b.perc_create(96, 0.5, 1)
+    other = b.perc_create(64, 0.5, 1)
+    try:
+        b.perc_set_params(ctx, 96, 0.62, 7, b.PERC_SOURCE_POINT, 40, 41)
+        b.perc_run(ctx)
+        arr = b.perc_copy_arrival(ctx, 96)
+        pore = o.perc_medium(96, 0.62, 7)
+        assert np.array_equal(arr, o.perc_invade(pore, 1, 40, 41))
+        for bad in (dict(L=95, porosity=0.5), dict(L=96, porosity=1.5), dict(L=96, porosity=0.5, source=1, i0=96)):
+            with pytest.raises(b.IsingError) as e:
+                b.perc_set_params(ctx, **bad)
+            assert e.value.code == b.ISING_EINVAL
+        with pytest.raises(b.IsingError) as e:
+            b.perc_run_batch([ctx, other, ctx])
+        assert e.value.code == b.ISING_EINVAL
+        b.perc_run_batch([])
+    finally:
+        b.perc_destroy(ctx)
+        b.perc_destroy(other)
+
+
+def test_batched_spanning_thresholds_equal_oracle(b, o):
+    """The spanning-threshold bisection run for 40 media of 128^2 at once
+    (one batched run per bisection step, porosities changed in place)
+    gives the oracle's per-seed thresholds exactly."""
+    from tests.test_oracle_percolation import _span_threshold
+    n, L = 40, 128
+    G.log("batched spanning thresholds, 40 media of 128^2")
+    lo, hi = np.full(n, 0.3), np.full(n, 0.9)
+    ctxs = [b.perc_create(L, 0.5, s) for s in range(n)]
+    try:
+        for _ in range(14):
+            mid = 0.5 * (lo + hi)
+            for s, c in enumerate(ctxs):
+                b.perc_set_params(c, L, float(mid[s]), s)
+            b.perc_run_batch(ctxs)
+            sp = np.array([b.perc_result_get(c).spans & 1 for c in ctxs], dtype=bool)
+            hi = np.where(sp, mid, hi)
+            lo = np.where(sp, lo, mid)
+    finally:
+        for c in ctxs:
+            b.perc_destroy(c)
+    assert list(hi) == [_span_threshold(o, L, s) for s in range(n)]
