@@ -315,7 +315,7 @@ def run_creutz(b, torch, stream, sweeps, metropolis_value, cpu=True):
                          "algorithmic_bytes_per_sweep": 4.0 * N}}
 
 
-def run_percolation(b, cpu=True):
+def run_percolation(b, cpu=True, spanning=True):
     """Porous media of Section 2.3 (porosity 0.6): the paper's Figure 3
     size and the headline lattice size; the oracle (plain breadth-first
     search) timed on an 8192^2 medium of the same kind."""
@@ -341,6 +341,8 @@ def run_percolation(b, cpu=True):
                         "value": N * max(1, r.passes) / s / 1e9,
                         "unit": "site-passes/ns (one full pass per invasion step, as in Section 2.3)"}})
     res = {"runs": out}
+    if not spanning:
+        return res
     # the spanning threshold (Section 2.3): per-seed porosity from which the
     # medium spans, by bisection (14 halvings of [0.3, 0.9]), for 64 media of
     # the paper's Figure 3 size: all media in one batched run per step, and
@@ -473,7 +475,7 @@ def main():
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--epoch-sweeps", type=int, default=64)
     ap.add_argument("--creutz-sweeps", type=int, default=100)
-    ap.add_argument("--only", choices=["creutz", "percolation", "micro"], default=None,
+    ap.add_argument("--only", choices=["creutz", "percolation", "percolation-media", "micro"], default=None,
                     help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
@@ -495,6 +497,8 @@ def main():
             leg = run_creutz(b, torch, stream, args.creutz_sweeps, float("nan"), cpu=False)
         elif args.only == "percolation":
             leg = run_percolation(b, cpu=False)
+        elif args.only == "percolation-media":
+            leg = run_percolation(b, cpu=False, spanning=False)
         else:
             leg = run_micro(b, torch, stream)
         print(json.dumps({"leg": args.only, "result": leg}), flush=True)
