@@ -448,8 +448,20 @@ def run_micro(b, torch, stream):
             nbytes = (4 * side - 4 if border and side > 2 else side * side) * elem
             tr.append({"op": name, "lattice": side, "bytes": nbytes, "s": ms * 1e-3, "MB_per_s": nbytes / ms / 1e3})
         del host, dev
+    # Philox4x32-10 rate (the draws alone): 2^20 threads x 2048 calls
+    out = torch.empty(1 << 20, dtype=torch.int32, device="cuda")
+    b.mb_philox(out.data_ptr(), 1 << 20, 2048, 11, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(5):
+        b.mb_philox(out.data_ptr(), 1 << 20, 2048, 11, stream.cuda_stream)
+    e1.record(stream)
+    e1.synchronize()
+    calls_per_ns = 5 * (1 << 20) * 2048 / e0.elapsed_time(e1) / 1e6
+    philox = {"calls_per_ns": calls_per_ns, "site_updates_per_ns_if_only_draws": 4 * calls_per_ns,
+              "note": "one Philox4x32-10 call per four site updates; the draws alone cap the Metropolis sweep here"}
     copy_gbs = max(v["GB_per_s"] for v in vec if v["op"] == "=" and v["lattice"] == 8192)
-    return {"vector_ops": vec, "transfers": tr, "achievable_hbm_copy_GB_per_s": copy_gbs,
+    return {"vector_ops": vec, "transfers": tr, "achievable_hbm_copy_GB_per_s": copy_gbs, "philox": philox,
             "roofline": {"bound": "hbm", "achieved": copy_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": copy_gbs / HBM_PEAK_GBS, "traffic": None,
                          "kernel": "k_vec<copy>, 1 GiB float vector (8 bytes moved per float)"}}

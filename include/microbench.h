@@ -50,6 +50,15 @@ int mb_vector_op(uint32_t op, float* a, const float* c, size_t n, void* stream);
 int mb_copy_lattice(void* dst, const void* src, uint32_t L, uint32_t elem, uint32_t direction, int border,
                     void* stream);
 
+/* Philox4x32-10 rate: n_threads threads each evaluate calls_per_thread
+ * Philox calls with counter (thread, k, 0, 0) and key (seed low, seed high),
+ * k = 0 .. calls_per_thread-1, and write the XOR of all words they drew to
+ * out[thread] (device, n_threads uint32). The draw is the one every site
+ * update of the Metropolis sweep needs (one call per four sites), so
+ * 4 x calls per second is the update rate the draws alone allow. Errors:
+ * EINVAL (NULL out, n_threads == 0 or > 2^31), EDEVICE. */
+int mb_philox(uint32_t* out, size_t n_threads, uint32_t calls_per_thread, uint64_t seed, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

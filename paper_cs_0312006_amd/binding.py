@@ -111,6 +111,7 @@ SIGNATURES = {
     "mb_vector_op": (C.c_int, [C.c_uint32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "mb_copy_lattice": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_int,
                                   C.c_void_p]),
+    "mb_philox": (C.c_int, [C.c_void_p, C.c_size_t, C.c_uint32, C.c_uint64, C.c_void_p]),
     "ising_strerror": (C.c_char_p, [C.c_int]),
     "ising_device_error": (C.c_char_p, [C.c_void_p]),
 }
@@ -346,6 +347,10 @@ def mb_vector_op(op, a_ptr, c_ptr, n, stream=None):
 def mb_copy_lattice(dst_ptr, src_ptr, L, elem, direction, border=False, stream=None):
     _check(lib().mb_copy_lattice(dst_ptr, src_ptr, int(L), int(elem), int(direction), 1 if border else 0, stream),
            "mb_copy_lattice")
+
+
+def mb_philox(out_ptr, n_threads, calls_per_thread, seed=0, stream=None):
+    _check(lib().mb_philox(out_ptr, int(n_threads), int(calls_per_thread), int(seed), stream), "mb_philox")
 
 
 def ising_strerror(code):

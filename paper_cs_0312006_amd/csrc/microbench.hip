@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ising_device.hpp"
 #include "microbench.h"
 
 namespace {
@@ -55,9 +56,32 @@ hipError_t launch(float* a, const float* c, size_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(kThreads) k_philox(uint32_t* out, uint32_t n, uint32_t calls, uint32_t k0,
+                                                     uint32_t k1) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= n) return;
+    uint32_t acc = 0;
+    for (uint32_t k = 0; k < calls; ++k) {
+        const uint4 r = ising::philox(tid, k, 0u, 0u, k0, k1);
+        acc ^= ising::xor3(r.x, r.y, r.z) ^ r.w;
+    }
+    out[tid] = acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+int mb_philox(uint32_t* out, size_t n_threads, uint32_t calls_per_thread, uint64_t seed, void* stream) {
+    if (!out || n_threads == 0 || n_threads > (size_t)1 << 31) return ISING_EINVAL;
+    const uint32_t n = (uint32_t)n_threads;
+    k_philox<<<(n + kThreads - 1) / kThreads, kThreads, 0, (hipStream_t)stream>>>(out, n, calls_per_thread,
+                                                                                  (uint32_t)seed,
+                                                                                  (uint32_t)(seed >> 32));
+    if (hipGetLastError() != hipSuccess) return ISING_EDEVICE;
+    return ISING_OK;
+}
+
 
 int mb_vector_op(uint32_t op, float* a, const float* c, size_t n, void* stream) {
     if (op > MB_OP_EXP || !a) return ISING_EINVAL;

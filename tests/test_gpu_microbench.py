@@ -76,3 +76,22 @@ def test_transfers_whole_and_border(env, L, elem):
     b.mb_copy_lattice(back.data_ptr(), dev.data_ptr(), L, elem, b.MB_DEVICE_TO_HOST, border=False)
     torch.cuda.synchronize()
     assert np.array_equal(back.numpy(), host.numpy())
+
+
+def test_philox_rate_kernel_draws_philox(env):
+    """The Philox-rate kernel evaluates the same draws as the NumPy Philox:
+    each thread's XOR of the words of counters (thread, k, 0, 0)."""
+    from oracle import mini
+    b, torch = env
+    n, calls, seed = 1000, 5, 0x1234567890ABCDEF
+    out = torch.zeros(n, dtype=torch.int32, device="cuda")
+    G.log("philox rate kernel n=1000 calls=5")
+    b.mb_philox(out.data_ptr(), n, calls, seed)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    tid = np.arange(n, dtype=np.uint64)
+    acc = np.zeros(n, dtype=np.uint64)
+    for k in range(calls):
+        w = mini.philox4x32_10(tid, k, 0, 0, seed & 0xFFFFFFFF, seed >> 32)
+        acc ^= w[0] ^ w[1] ^ w[2] ^ w[3]
+    assert np.array_equal(got, acc.astype(np.uint32))
