@@ -130,11 +130,13 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(const Medium* __restric
     const uint32_t hx0 = (threadIdx.x / kTile) * kStrip;
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         const uint2 ent = w.list[pin][e];
-        const uint32_t m = ent.x, tile = ent.y;
-        const Medium md = media[m];
+        // the entry is the same for the whole workgroup: keep it scalar
+        const uint32_t m = (uint32_t)__builtin_amdgcn_readfirstlane((int)ent.x);
+        const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)ent.y);
+        const Medium& md = media[m];
         uint32_t* const arr = md.arr;
         const uint32_t L = md.L, n_tx = md.n_tx, n_ty = md.n_ty;
-        uint32_t* q_in = md.queued[pin];
+        uint32_t* q_in = pin ? md.queued[1] : md.queued[0];
         const uint32_t ty = tile / n_tx, tx = tile - ty * n_tx;
         const int64_t gi0 = (int64_t)ty * kTile - 1, gj0 = (int64_t)tx * kTile - 1;  // halo origin
         if (threadIdx.x == 0) q_in[tile] = 0u;
@@ -242,7 +244,7 @@ __global__ void __launch_bounds__(kThreads) k_perc_relax(const Medium* __restric
         rgt = __syncthreads_or(rgt);
         if (threadIdx.x == 0) {
             const uint32_t par = pin ^ 1u;
-            uint32_t* q_out = md.queued[par];
+            uint32_t* q_out = par ? md.queued[1] : md.queued[0];
             if (top && ty > 0) push(w, q_out, par, lout, m, tile - n_tx);
             if (bot && ty + 1 < n_ty) push(w, q_out, par, lout, m, tile + n_tx);
             if (lft && tx > 0) push(w, q_out, par, lout, m, tile - 1);
