@@ -111,6 +111,17 @@ def test_kaufman_formula_matches_enumeration():
             assert abs(physics.kaufman_energy(L, T) - physics.exact_averages(L, 1.0, 0.0, T)["e"]) < 1e-10
 
 
+def test_kaufman_and_onsager_reference_values():
+    """The finite-lattice (Kaufman) and infinite-lattice (Onsager) energies
+    per site at L = 64, T = 2.269185, against reference values computed
+    independently of this code: the 64 x 64
+    torus sits 0.0097 below the infinite lattice, far beyond any Monte
+    Carlo standard error, which is why tests at this temperature use
+    Kaufman's formula."""
+    assert abs(physics.kaufman_energy(64, 2.269185) - (-1.42393907865393)) < 1e-13
+    assert abs(physics.onsager_energy(2.269185) - (-1.41421607553601)) < 1e-13
+
+
 def test_infinite_temperature_flips_everything(oracle):
     """T -> infinity: every threshold is 2^32, each pass flips its colour, so
     after sweep t the lattice is (-1)^(t+1) s_0; B is unchanged, M alternates."""
