@@ -53,17 +53,20 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
-// Philox4x32-10 (Salmon et al., SC 2011) of counter (q, c1, c2, c3) and key
-// (k0, k1). Only q varies across lanes in this engine; c1..c3 and the key are
-// wave-uniform, so the uniform halves of the first rounds stay on the scalar
-// unit and the vector cost is about 37 ops per call: each later round is two
-// 32x32->64 multiplies (v_mad_u64_u32) and two three-way XORs.
-__device__ __forceinline__ uint4 philox(uint32_t q, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
-    uint32_t x0 = q, x1 = c1, x2 = c2, x3 = c3;
+// Philox4x32-10 (Salmon et al., SC 2011) of counter (x0, c1, c2, c3) and key
+// (k0, k1), given the first round's product p0 = M0 * x0 (64-bit). Only x0
+// varies across lanes in this engine; c1..c3 and the key are wave-uniform,
+// so the uniform halves of the first rounds stay on the scalar unit and the
+// vector cost is about 37 ops per call: each later round is two 32x32->64
+// multiplies (v_mad_u64_u32) and two three-way XORs. Callers whose x0 is a
+// uniform part plus a lane part pass p0 = M0 * lane + M0 * uniform, one
+// multiply-add (x0 < 2^32 without wrap, so the two products agree).
+__device__ __forceinline__ uint4 philox_p0(uint64_t p0_first, uint32_t c1, uint32_t c2, uint32_t c3,
+                                           uint32_t k0, uint32_t k1) {
+    uint32_t x0 = 0, x1 = c1, x2 = c2, x3 = c3;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * x0;
+        const uint64_t p0 = r == 0 ? p0_first : (uint64_t)kPhiloxM0 * x0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * x2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), hi1 = (uint32_t)(p1 >> 32);
         uint32_t y0, y2;
@@ -85,6 +88,12 @@ __device__ __forceinline__ uint4 philox(uint32_t q, uint32_t c1, uint32_t c2, ui
         k1 += kPhiloxW1;
     }
     return make_uint4(x0, x1, x2, x3);
+}
+
+// Philox4x32-10 of counter (q, c1, c2, c3) and key (k0, k1).
+__device__ __forceinline__ uint4 philox(uint32_t q, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1) {
+    return philox_p0((uint64_t)kPhiloxM0 * q, c1, c2, c3, k0, k1);
 }
 
 // Acceptance tables, indexed by code = 8*s + n (s = spin bit, n = number of
@@ -117,12 +126,11 @@ __device__ __forceinline__ T lds_at(const T* base, uint32_t byte_off) {
 }
 
 // Flip mask of one word of four sites: byte b is 1 when site b's move is
-// accepted. W holds the four spin bits, n the four up-neighbour counts and
-// r the four draws of the word's Philox call.
+// accepted. code4 holds 4 * (8 s + n) per byte (s the spin bit, n the number
+// of up neighbours) and r the four draws of the word's Philox call.
 template <bool EXACT>
-__device__ __forceinline__ uint32_t flip_mask(const LdsTable& lt, uint32_t W, uint32_t n, uint4 r) {
+__device__ __forceinline__ uint32_t flip_mask_code(const LdsTable& lt, uint32_t code4, uint4 r) {
     if (!EXACT) {
-        const uint32_t code4 = (W << 5) | (n << 2);  // per byte: 4 * (8 s + n)
         const uint32_t a0 = lds_at(lt.t32, code4 & 0xffu);
         const uint32_t a1 = lds_at(lt.t32, (code4 >> 8) & 0xffu);
         const uint32_t a2 = lds_at(lt.t32, (code4 >> 16) & 0xffu);
@@ -133,7 +141,7 @@ __device__ __forceinline__ uint32_t flip_mask(const LdsTable& lt, uint32_t W, ui
         const uint32_t f3 = r.w <= a3 ? 0x01000000u : 0u;
         return (f0 | f1) | (f2 | f3);
     } else {
-        const uint32_t code8 = (W << 6) | (n << 3);  // per byte: 8 * (8 s + n)
+        const uint32_t code8 = code4 << 1;  // per byte: 8 * (8 s + n) <= 96
         const uint2 a0 = lds_at(lt.t64, code8 & 0xffu);
         const uint2 a1 = lds_at(lt.t64, (code8 >> 8) & 0xffu);
         const uint2 a2 = lds_at(lt.t64, (code8 >> 16) & 0xffu);
@@ -147,6 +155,12 @@ __device__ __forceinline__ uint32_t flip_mask(const LdsTable& lt, uint32_t W, ui
         const uint32_t f3 = lt64(r.w, a3) ? 0x01000000u : 0u;
         return (f0 | f1) | (f2 | f3);
     }
+}
+
+// The same from the spin bits W and the up-neighbour counts n.
+template <bool EXACT>
+__device__ __forceinline__ uint32_t flip_mask(const LdsTable& lt, uint32_t W, uint32_t n, uint4 r) {
+    return flip_mask_code<EXACT>(lt, (W << 5) | (n << 2), r);
 }
 
 // Same-row neighbour word: bytes m+1..m+4 (p == 1) or m-1..m+2 (p == 0) of
@@ -163,6 +177,11 @@ __device__ __forceinline__ uint32_t shifted(uint32_t O, uint32_t O_next, uint32_
 // one v_sad_u8.
 __device__ __forceinline__ uint32_t sad_misaligned(uint32_t Wn, uint32_t n, uint32_t acc) {
     return __builtin_amdgcn_sad_u8(Wn << 2, n, acc);
+}
+
+// The same from n4 = 4 n per byte; adds 4 * sum_b |4 s_b - n_b|.
+__device__ __forceinline__ uint32_t sad_misaligned4(uint32_t Wn, uint32_t n4, uint32_t acc) {
+    return __builtin_amdgcn_sad_u8(Wn << 4, n4, acc);
 }
 
 // Pointers read from descriptors in memory are generic; naming the global

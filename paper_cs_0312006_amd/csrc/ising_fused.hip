@@ -16,6 +16,11 @@
 //     recomputed (two extra row updates per tile).
 // Recomputed sites use the same counter-based draws as their owners, so the
 // result is bit-identical to any other schedule of the same sweep.
+//
+// Row traffic goes through buffer resources: a plane is one raw buffer, the
+// lane's byte offset within a row is fixed for the whole tile and the row's
+// byte offset is a scalar, so loads and stores cost no vector instructions
+// for addressing (a plane is at most 2^31 bytes).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,42 +49,60 @@ struct Row {
     uint32_t v[CW];
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Raw buffer over a whole plane; word 3 is the gfx9 resource format for
+// untyped 32-bit data.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const uint32_t* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(p), 0, -1, 0x00020000);
+}
+
+// CW words at byte offset xb (lane) + soff (row, uniform) of a plane.
 template <int CW>
-__device__ __forceinline__ Row<CW> ld(const uint32_t* __restrict__ p) {
+__device__ __forceinline__ Row<CW> ld(__amdgpu_buffer_rsrc_t rs, uint32_t xb, uint32_t soff) {
     Row<CW> r;
     if constexpr (CW == 4) {
-        const uint4 x = *reinterpret_cast<const uint4*>(p);
-        r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, xb, soff, 0);
+        r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
     } else if constexpr (CW == 2) {
-        const uint2 x = *reinterpret_cast<const uint2*>(p);
-        r.v[0] = x.x; r.v[1] = x.y;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, xb, soff, 0);
+        r.v[0] = v.x; r.v[1] = v.y;
     } else {
-#pragma unroll
-        for (int w = 0; w < CW; ++w) r.v[w] = p[w];
+        r.v[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, xb, soff, 0);
     }
     return r;
 }
 
+// CW words to byte offset off of a plane. The whole offset is in the vector
+// operand and the scalar offset is the constant 0: a store wider than 64
+// bits reads part of its data registers after issue, and with a register in
+// the scalar offset field the compiler does not keep the next instructions
+// from overwriting them (seen on gfx950 as wrong words in the last lanes of
+// each group of 16); with a constant there it does.
 template <int CW>
-__device__ __forceinline__ void st(uint32_t* __restrict__ p, const Row<CW>& r) {
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t rs, uint32_t off, const Row<CW>& r) {
     if constexpr (CW == 4) {
-        *reinterpret_cast<uint4*>(p) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+        const u32x4 v = {r.v[0], r.v[1], r.v[2], r.v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
     } else if constexpr (CW == 2) {
-        *reinterpret_cast<uint2*>(p) = make_uint2(r.v[0], r.v[1]);
+        const u32x2 v = {r.v[0], r.v[1]};
+        __builtin_amdgcn_raw_buffer_store_b64(v, rs, off, 0, 0);
     } else {
-#pragma unroll
-        for (int w = 0; w < CW; ++w) p[w] = r.v[w];
+        __builtin_amdgcn_raw_buffer_store_b32(r.v[0], rs, off, 0, 0);
     }
 }
 
 // Update one lane's CW words of a plane row. P = (i + c) & 1 selects the
 // same-row neighbour side; `edge` is the word just outside the tile on that
-// side (right for P == 1, left for P == 0) of the `same` row.
+// side (right for P == 1, left for P == 0) of the `same` row. Word w's draw
+// counter is q = (row offset) + xw[w]; m0row = M0 * (row offset), so the
+// first Philox product M0 * q is one multiply-add per word.
 template <int CW, bool EXACT, int P, bool OBS>
 __device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>& own, const Row<CW>& up,
                                               const Row<CW>& dn, const Row<CW>& same, uint32_t edge,
-                                              uint32_t q0, uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
-                                              uint32_t& sad) {
+                                              const Row<CW>& xw, uint64_t m0row, uint32_t t, uint32_t c,
+                                              uint32_t k0, uint32_t k1, uint32_t& sad) {
     const uint32_t nb = P ? from_right(same.v[0], edge) : from_left(same.v[CW - 1], edge);
     Row<CW> out;
 #pragma unroll
@@ -92,21 +115,17 @@ __device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>&
             const uint32_t prv = (w > 0) ? same.v[(w > 0) ? w - 1 : 0] : nb;
             S = __builtin_amdgcn_alignbyte(same.v[w], prv, 3);
         }
-        const uint32_t n = up.v[w] + dn.v[w] + same.v[w] + S;
-        const uint4 r = philox(q0 + (uint32_t)w, t, c, 0u, k0, k1);
-        const uint32_t Wn = own.v[w] ^ flip_mask<EXACT>(lt, own.v[w], n, r);
+        // table offset 4 (8 s + n) = ((8 s + three neighbours) + fourth) << 2:
+        // add3, shift-add, add-shift
+        const uint32_t t3 = up.v[w] + dn.v[w] + S;
+        const uint32_t code4 = (((own.v[w] << 3) + t3) + same.v[w]) << 2;
+        const uint32_t n4 = (t3 + same.v[w]) << 2;  // 4 n per byte (colour-1 observables only)
+        const uint4 r = philox_p0((uint64_t)kPhiloxM0 * xw.v[w] + m0row, t, c, 0u, k0, k1);
+        const uint32_t Wn = own.v[w] ^ flip_mask_code<EXACT>(lt, code4, r);
         out.v[w] = Wn;
-        if (OBS) sad = sad_misaligned(Wn, n, sad);
+        if (OBS) sad = sad_misaligned4(Wn, n4, sad);
     }
     return out;
-}
-
-template <int CW>
-__device__ __forceinline__ uint32_t popc(const Row<CW>& r) {
-    uint32_t s = 0;
-#pragma unroll
-    for (int w = 0; w < CW; ++w) s += __builtin_popcount(r.v[w]);
-    return s;
 }
 
 __device__ __forceinline__ uint32_t wrap_row(int i, uint32_t L) {
@@ -146,7 +165,6 @@ __global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, Part
     uint32_t* __restrict__ d1 = a.dst1;
 
     auto row_ptr = [&](const uint32_t* base, int i) { return base + (size_t)wrap_row(i, L) * Hw; };
-    auto out_ptr = [&](uint32_t* base, int i) { return base + (size_t)wrap_row(i, L) * Hw; };
 
     // Old colour-1 word just outside the tile that the colour-0 update of
     // row j = r0 + 1 + lane needs: right of the tile for odd j, left for even j.
@@ -178,7 +196,17 @@ __global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, Part
         edge_c0 = own ^ flip_mask<EXACT>(lt, own, n, r);
     }
 
-    uint32_t sad = 0, ups = 0, dummy = 0;
+    uint32_t sad = 0, ups = 0, ups8 = 0, dummy = 0;
+    const uint32_t xb = x * 4u;  // lane's byte offset within a row
+    Row<CW> xw;                  // lane's word indices within a row
+#pragma unroll
+    for (int w = 0; w < CW; ++w) xw.v[w] = x + (uint32_t)w;
+    const __amdgpu_buffer_rsrc_t rs0 = plane_rsrc(s0), rs1 = plane_rsrc(s1);
+    const __amdgpu_buffer_rsrc_t rd0 = plane_rsrc(d0), rd1 = plane_rsrc(d1);
+    // word offset of row i (wrapped), its byte offset, and M0 times it
+    auto rword = [&](int i) { return wrap_row(i, L) * Hw; };
+    auto rbyte = [&](int i) { return rword(i) * 4u; };
+    auto m0row = [&](int i) { return (uint64_t)kPhiloxM0 * rword(i); };
     // Ring buffers, indexed by compile-time slots in a loop unrolled by 4,
     // so that a prefetched row is never copied between registers (a copy
     // would force a wait on the load):
@@ -186,22 +214,22 @@ __global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, Part
     //   c0o[(row - r0) & 1]     old colour-0 rows
     //   c0n[(row - r0 + 1) & 3] new colour-0 rows
     Row<CW> c1[4], c0o[2], c0n[4];
-    const Row<CW> c1m2 = ld<CW>(row_ptr(s1, r0 - 2) + x);
-    const Row<CW> c1m1 = ld<CW>(row_ptr(s1, r0 - 1) + x);
-    c1[0] = ld<CW>(row_ptr(s1, r0) + x);
-    c1[1] = ld<CW>(row_ptr(s1, r0 + 1) + x);
-    c1[2] = ld<CW>(row_ptr(s1, r0 + 2) + x);
-    const Row<CW> c0om1 = ld<CW>(row_ptr(s0, r0 - 1) + x);
-    c0o[0] = ld<CW>(row_ptr(s0, r0) + x);
-    c0o[1] = ld<CW>(row_ptr(s0, r0 + 1) + x);
+    const Row<CW> c1m2 = ld<CW>(rs1, xb, rbyte(r0 - 2));
+    const Row<CW> c1m1 = ld<CW>(rs1, xb, rbyte(r0 - 1));
+    c1[0] = ld<CW>(rs1, xb, rbyte(r0));
+    c1[1] = ld<CW>(rs1, xb, rbyte(r0 + 1));
+    c1[2] = ld<CW>(rs1, xb, rbyte(r0 + 2));
+    const Row<CW> c0om1 = ld<CW>(rs0, xb, rbyte(r0 - 1));
+    c0o[0] = ld<CW>(rs0, xb, rbyte(r0));
+    c0o[1] = ld<CW>(rs0, xb, rbyte(r0 + 1));
     const uint32_t eR = row_ptr(s1, r0 - 1)[xr];
     const uint32_t eL = row_ptr(s1, r0)[xl];
     // new colour-0 rows r0-1 (odd: same-row side P = 1) and r0 (even: P = 0)
-    c0n[0] = update_row<CW, EXACT, 1, false>(lt, c0om1, c1m2, c1[0], c1m1, eR, wrap_row(r0 - 1, L) * Hw + x, t,
-                                             0u, k0, k1, dummy);
-    c0n[1] = update_row<CW, EXACT, 0, false>(lt, c0o[0], c1m1, c1[1], c1[0], eL, wrap_row(r0, L) * Hw + x, t, 0u,
-                                             k0, k1, dummy);
-    st<CW>(out_ptr(d0, r0) + x, c0n[1]);
+    c0n[0] = update_row<CW, EXACT, 1, false>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, m0row(r0 - 1), t, 0u, k0, k1,
+                                             dummy);
+    c0n[1] = update_row<CW, EXACT, 0, false>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, m0row(r0), t, 0u, k0, k1,
+                                             dummy);
+    st<CW>(rd0, xb + rbyte(r0), c0n[1]);
 
 #pragma unroll 1
     for (int k = 0; k < R; k += 4) {
@@ -210,36 +238,41 @@ __global__ void __launch_bounds__(256) k_fused(FusedArgs a, AcceptTable at, Part
             const int i = r0 + k + u;
             // prefetch old colour-1 row i+3 and old colour-0 row i+2 into the
             // slots of rows i-1 and i, which this step no longer reads
-            c1[(u + 3) & 3] = ld<CW>(row_ptr(s1, i + 3) + x);
-            c0o[u & 1] = ld<CW>(row_ptr(s0, i + 2) + x);
+            c1[(u + 3) & 3] = ld<CW>(rs1, xb, rbyte(i + 3));
+            c0o[u & 1] = ld<CW>(rs0, xb, rbyte(i + 2));
             const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c1, k + u);
             const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c0, k + u);
-            const uint32_t q1 = wrap_row(i + 1, L) * Hw + x;
-            const uint32_t q0 = wrap_row(i, L) * Hw + x;
+            const uint64_t m1 = m0row(i + 1);
+            const uint64_t m0 = m0row(i);
             Row<CW> c1n;
             if ((u & 1) == 0) {  // i even: both updates have same-row side P = 1
                 c0n[(u + 2) & 3] = update_row<CW, EXACT, 1, false>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
-                                                                   c1[(u + 1) & 3], e1, q1, t, 0u, k0, k1, dummy);
+                                                                   c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy);
                 c1n = update_row<CW, EXACT, 1, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3], c0n[(u + 1) & 3],
-                                                     e0, q0, t, 1u, k0, k1, sad);
+                                                     e0, xw, m0, t, 1u, k0, k1, sad);
             } else {
                 c0n[(u + 2) & 3] = update_row<CW, EXACT, 0, false>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
-                                                                   c1[(u + 1) & 3], e1, q1, t, 0u, k0, k1, dummy);
+                                                                   c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy);
                 c1n = update_row<CW, EXACT, 0, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3], c0n[(u + 1) & 3],
-                                                     e0, q0, t, 1u, k0, k1, sad);
+                                                     e0, xw, m0, t, 1u, k0, k1, sad);
             }
-            if (k + u + 1 < R) st<CW>(out_ptr(d0, i + 1) + x, c0n[(u + 2) & 3]);
-            st<CW>(out_ptr(d1, i) + x, c1n);
-            ups += popc<CW>(c1n) + popc<CW>(c0n[(u + 1) & 3]);
+            if (k + u + 1 < R) st<CW>(rd0, xb + rbyte(i + 1), c0n[(u + 2) & 3]);
+            st<CW>(rd1, xb + rbyte(i), c1n);
+            // up spins of both new rows, byte-wise (at most 8 CW <= 32 per
+            // byte over the four steps of k)
+#pragma unroll
+            for (int w = 0; w < CW; ++w) ups8 += c1n.v[w] + c0n[(u + 1) & 3].v[w];
             // keep the next step's use of this step's prefetch after this
             // step's work, so the load has a whole step to arrive
             __builtin_amdgcn_sched_barrier(0);
         }
+        ups = __builtin_amdgcn_sad_u8(ups8, 0u, ups);
+        ups8 = 0;
     }
 
-    // per-wave partials: B = 16 * words - 2 * sad, M = 2 * ups - 8 * words
+    // per-wave partials: B = 16 * words - 2 * (sad / 4), M = 2 * ups - 8 * words
     const int64_t words = (int64_t)R * CW;
-    int64_t b = 16 * words - 2 * (int64_t)sad;
+    int64_t b = 16 * words - (int64_t)(sad >> 1);
     int64_t m = 2 * (int64_t)ups - 8 * words;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {

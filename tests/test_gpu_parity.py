@@ -236,6 +236,40 @@ def test_c1_4096_full_length(b, o, k):
         assert abs(e.mean() - physics.kaufman_energy(run.L, run.T)) < 0.03
 
 
+FUSED_SHAPES = [(cw, rows) for cw in (1, 2, 4) for rows in (8, 16, 32, 64)]
+
+
+@pytest.mark.parametrize("L", [8192, 16384])
+def test_every_fused_tile_shape(b, o, L):
+    """Every tile shape of the fused one-pass sweep (words per lane x rows
+    per tile) gives the two-pass plan's lattice, hash and per-sweep (B, M)
+    bit for bit, from a cold start (h = 0) and a hot start (h = 0.1), over 12
+    sweeps; at 8192 the two-pass result is also the oracle's. This covers the
+    tile shapes the autotuner can pick at the large sides, where the launch
+    has thousands of tiles in flight."""
+    for h, p_up in ((0.0, 1.0), (0.1, 0.5)):
+        run = W.Run(L=L, h=h, T=W.T_C_CONFIG, seed=11, p_up=p_up, sweeps=12)
+        G.log(f"fused shapes L={L} h={h} p_up={p_up}: two-pass reference")
+        ref = G.gpu_run(b, run, plan=b.ISING_PLAN_TWO_PASS)
+        if L == 8192:
+            G.assert_same(ref, G.oracle_run(o, run), f"two-pass {L}")
+        for cw, rows in FUSED_SHAPES:
+            if (L // 8) % (64 * cw) or L % rows:
+                continue
+            G.log(f"fused shapes L={L} h={h} p_up={p_up}: <{cw},{rows}>")
+            ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+            try:
+                b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, cw, rows)
+                b.ising_sweep(ctx, run.sweeps)
+                obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+                spins = b.ising_copy_spins(ctx, run.L)
+                assert tuple(b.ising_plan_info(ctx)) == (b.ISING_PLAN_FUSED, cw, rows)
+            finally:
+                b.ising_destroy(ctx)
+            G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref,
+                          f"fused <{cw},{rows}> L={L} h={h}")
+
+
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_c2_32768_sampled(b, o, k):
     """32768 x 32768 (1 GiB), 500 sweeps, for h in {0, 0.1} x {cold, hot}:
