@@ -29,24 +29,24 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit op
 # sources (profiles/k_fused_ising2d_32768.md), per tile shape. They are
 # reported only while the kernel sources hash to the recorded value and the
 # timed plan is one of these; otherwise they are null.
-PROFILED_SOURCES = "9169ba37a72ee186"
+PROFILED_SOURCES = "900b07393d265678"
 PROFILED = {
     # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch, mean of 54)
-    "k_fused<4,32>": {"hbm_bytes_per_launch": (698114.6 * 2.0 + 1048845.5) * 1024,
-                      "valu_lane_ops_per_attempt": 277456490.4 * 64 / 2 ** 30,
-                      "valu_busy_rocprof": 0.971},
+    "k_fused<4,32>": {"hbm_bytes_per_launch": (690127.8 * 2.0 + 1048863.4) * 1024,
+                      "valu_lane_ops_per_attempt": 256517738.4 * 64 / 2 ** 30,
+                      "valu_busy_rocprof": 0.942},
     # mean of 52
-    "k_fused<4,16>": {"hbm_bytes_per_launch": (745646.1 * 2.0 + 1049109.3) * 1024,
-                      "valu_lane_ops_per_attempt": 289885138.0 * 64 / 2 ** 30,
-                      "valu_busy_rocprof": 0.993},
+    "k_fused<4,16>": {"hbm_bytes_per_launch": (741900.8 * 2.0 + 1049112.3) * 1024,
+                      "valu_lane_ops_per_attempt": 268323794.0 * 64 / 2 ** 30,
+                      "valu_busy_rocprof": 0.990},
 }
 
 
 # Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md),
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch, mean of 22
-PROFILED_CREUTZ_SOURCES = "9125b02e811f5446"
+PROFILED_CREUTZ_SOURCES = "ec89c70e827bb88f"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
-                   "hbm_bytes_per_sweep": (1316787.4 * 2.0 + 2097588.4) * 1024}
+                   "hbm_bytes_per_sweep": (1316828.2 * 2.0 + 2097585.8) * 1024}
 
 
 def kernel_sources_hash(files=("ising_fused.hip", "ising_device.hpp", "ising_launch.hpp")):
