@@ -161,23 +161,27 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * (NULL: the first context's stream), with the batch plan ISING_BATCH_AUTO
  * picks (see ising_sweep_batch_plan): one persistent launch from a captured
  * graph in which each workgroup takes whole lattices, largest work first,
- * and runs all of their sweeps, or, when some side is above 256, graph
- * replays of passes that spread every lattice over the whole GPU. The
- * descriptors are staged with one host-to-device copy. Lattices may differ
- * in L, J, h, T and seed; each must satisfy L % 8 == 0 and have no pending
- * device error. Contexts are validated before anything is launched
- * (all-or-nothing). The results are bit-identical to calling ising_sweep on
- * each context alone. Asynchronous; the contexts' own streams are ordered
- * after it. */
+ * and runs all of their sweeps from its local memory, or, when some lattice
+ * is too large for that, graph replays of passes that spread every lattice
+ * over the whole GPU. The descriptors are staged with one host-to-device
+ * copy. Lattices may differ in L, J, h, T and seed; each must satisfy
+ * L % 8 == 0 and have no pending device error. Contexts are validated
+ * before anything is launched (all-or-nothing). The results are
+ * bit-identical to calling ising_sweep on each context alone. Asynchronous;
+ * the contexts' own streams are ordered after it. */
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream);
 
 /* As ising_sweep_batch with an explicit batch plan:
  * ISING_BATCH_RESIDENT: one persistent launch, each workgroup runs whole
- *   lattices (every sweep) taken from a work queue, largest first;
+ *   lattices (every sweep) taken from a work queue, largest first. A lattice
+ *   with h = 0 and side up to 1072 is held in the workgroup's local memory
+ *   at one bit per site for all its sweeps; other lattices of side up to 256
+ *   are held there as bytes; larger ones are swept in global memory;
  * ISING_BATCH_STEPPED: every colour pass is one launch over the chunks of
  *   all lattices, so each lattice is spread over the whole GPU; sweeps are
  *   replayed from a captured graph in groups of 16;
- * ISING_BATCH_AUTO: resident when every side is <= 256, else stepped.
+ * ISING_BATCH_AUTO: resident when every lattice is held in local memory
+ *   (side <= 256, or h = 0 and side <= 1072), else stepped.
  * Results are identical for every plan. */
 #define ISING_BATCH_AUTO 0u
 #define ISING_BATCH_RESIDENT 1u

@@ -4,10 +4,15 @@
 // orders the queue by work, largest first) and runs all of that lattice's
 // sweeps itself: colour 0 of sweep t, a workgroup barrier, colour 1, a
 // barrier, then the sweep's (B, M) (Section 2.2's consecutive black and
-// white passes). Lattices stay in their own colour planes and are updated
-// in place; small ones live in the L1/L2 of the workgroup's CU for the whole
-// run. The grid is sized to the resident capacity of the chip, so the kernel
-// is persistent: no workgroup waits on another.
+// white passes). The grid is sized to the resident capacity of the chip, so
+// the kernel is persistent: no workgroup waits on another.
+//
+// Where a lattice lives while it is swept:
+//   - h = 0 lattices whose two colour planes fit this workgroup's LDS at one
+//     bit per site (sides up to 1072) are converted to bits, swept there for
+//     all their sweeps and converted back (the bit-packed path below);
+//   - other lattices of at most 64 KiB are copied to LDS as bytes;
+//   - the rest are swept in place in global memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -18,7 +23,7 @@ namespace ising {
 
 namespace {
 
-constexpr uint32_t kBatchThreads = 512;
+constexpr uint32_t kBatchThreads = 1024;
 
 template <int CW, bool OBS, bool EXACT, typename PT>
 __device__ __forceinline__ void colour_pass(const LdsTable& lt, const BatchItem& it, PT p0, PT p1, uint32_t c,
@@ -114,6 +119,221 @@ __device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem&
     if (rem) flush(it.n - rem, rem);
 }
 
+// ---------------------------------------------------------------------------
+// Bit-packed path. Plane c of an L x L lattice is kept as L rows of Wr =
+// ceil(Hw / 8) 32-bit words; bit 4 j + b of word k of row i is the site of
+// byte m = 32 k + 4 j + b of the plane row (quad 8 k + j, Philox output b),
+// so a word holds the four draws of eight consecutive Philox calls. Bits
+// past the H = 4 Hw sites of a row are zero and stay zero.
+//
+// For h = 0 the acceptance threshold of a site depends only on the number m
+// of its neighbours that disagree with it (Delta E = 2 J (4 - 2 m) when it
+// flips), so a word's update is bitwise: the four disagreement masks give
+// the masks of the classes m = 0, 1 (J > 0) or m = 3, 4 (J < 0) whose
+// threshold is below one, each site's draw is compared with both class
+// thresholds (bit by bit, shifted into two masks of failed compares), and a
+// site flips unless it is in such a class and its compare failed. The draws and thresholds
+// are those of the byte kernels, so the results are the same bit for bit.
+
+// acc = 2 acc + (r > thr_m1): the borrow of thr_m1 - r shifted in, two VALU
+// operations (the compiler's own form of this takes three).
+__device__ __forceinline__ uint32_t shift_in_reject(uint32_t acc, uint32_t r, uint32_t thr_m1) {
+    uint32_t diff;
+    asm("v_sub_co_u32 %1, vcc, %3, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(acc), "=&v"(diff)
+        : "v"(r), "s"(thr_m1)
+        : "vcc");
+    return acc;
+}
+
+// One word's worth of the two threshold compares: bit 4 j + b of *ra (*rb)
+// is set when draw b of quad j fails class A's (B's) threshold.
+__device__ __forceinline__ void bits_compares(uint32_t q0, uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
+                                              uint32_t thra_m1, uint32_t thrb_m1, uint32_t& ra, uint32_t& rb) {
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        const uint4 r = philox(q0 + (uint32_t)j, t, c, 0u, k0, k1);
+        // highest bit first: after 32 steps bit 4 j + b holds site (j, b)
+        a = shift_in_reject(a, r.w, thra_m1);
+        b = shift_in_reject(b, r.w, thrb_m1);
+        a = shift_in_reject(a, r.z, thra_m1);
+        b = shift_in_reject(b, r.z, thrb_m1);
+        a = shift_in_reject(a, r.y, thra_m1);
+        b = shift_in_reject(b, r.y, thrb_m1);
+        a = shift_in_reject(a, r.x, thra_m1);
+        b = shift_in_reject(b, r.x, thrb_m1);
+    }
+    ra = a;
+    rb = b;
+}
+
+struct BitsLattice {
+    uint32_t L, Hw, Wr;
+    uint32_t hb;        // index of the last valid bit of a row's last word
+    uint32_t last_valid;  // valid-bit mask of a row's last word
+    uint32_t thra_m1, thrb_m1;  // class thresholds minus one (when not never)
+    bool never_a, never_b;
+    bool ferro;         // classes A, B are m = 1, 0 (else m = 3, 4)
+};
+
+// Colour pass c of sweep t over the bit planes at lat (plane c at c * L * Wr).
+template <bool OBS>
+__device__ __forceinline__ void bits_pass(uint32_t* __restrict__ lat, const BitsLattice& bl, uint32_t c,
+                                          uint32_t t, uint32_t k0, uint32_t k1, uint32_t& mis, uint32_t& ups) {
+    const uint32_t L = bl.L, Wr = bl.Wr, Hw = bl.Hw;
+    uint32_t* own_p = lat + c * L * Wr;
+    const uint32_t* oth_p = lat + (1u - c) * L * Wr;
+    const uint32_t rs = blockDim.x / Wr;  // rows per step
+    const uint32_t tid = threadIdx.x;
+    if (tid >= rs * Wr) return;
+    const uint32_t k = tid % Wr;
+    const bool last = k + 1 == Wr;
+    const uint32_t valid = last ? bl.last_valid : 0xffffffffu;
+    const uint32_t top = last ? bl.hb : 31u;
+    const uint32_t kn = last ? 0u : k + 1;       // next word of the row (wrapping)
+    const uint32_t kp = k == 0 ? Wr - 1 : k - 1;  // previous word of the row (wrapping)
+    const uint32_t top_p = k == 0 ? bl.hb : 31u;  // last valid bit of the previous word
+    for (uint32_t i = tid / Wr; i < L; i += rs) {
+        const uint32_t iu = i == 0 ? L - 1 : i - 1;
+        const uint32_t id = i + 1 == L ? 0 : i + 1;
+        const uint32_t own = own_p[i * Wr + k];
+        const uint32_t U = oth_p[iu * Wr + k];
+        const uint32_t D = oth_p[id * Wr + k];
+        const uint32_t O = oth_p[i * Wr + k];
+        const uint32_t On = oth_p[i * Wr + kn];
+        const uint32_t Op = oth_p[i * Wr + kp];
+        // same-row neighbour of site m: m + 1 when (i + c) is odd, else m - 1
+        const uint32_t s_up = (O >> 1) | ((On & 1u) << top);
+        const uint32_t s_dn = ((O << 1) | ((Op >> top_p) & 1u)) & valid;
+        const uint32_t S = ((i + c) & 1u) ? s_up : s_dn;
+        uint32_t ra, rb;
+        bits_compares(i * Hw + 8u * k, t, c, k0, k1, bl.thra_m1, bl.thrb_m1, ra, rb);
+        if (bl.never_a) ra = 0xffffffffu;
+        if (bl.never_b) rb = 0xffffffffu;
+        // disagreement masks and the two classes
+        const uint32_t a = own ^ U, b = own ^ D, d = own ^ O, e = own ^ S;
+        const uint32_t odd = a ^ b ^ d ^ e;
+        const uint32_t pair = (a & b) | (d & e);
+        uint32_t ea, eb;
+        if (bl.ferro) {
+            ea = odd & ~pair;       // exactly one disagrees
+            eb = ~(a | b | d | e);  // none
+        } else {
+            ea = odd & pair;        // exactly three
+            eb = a & b & d & e;     // all four
+        }
+        const uint32_t reject = (ea & ra) | (eb & rb);
+        const uint32_t nw = own ^ (valid & ~reject);
+        own_p[i * Wr + k] = nw;
+        if (OBS) {
+            // bonds of this colour-1 word, all final now, that disagree
+            mis += __builtin_popcount((nw ^ U) & valid) + __builtin_popcount((nw ^ D) & valid) +
+                   __builtin_popcount((nw ^ O) & valid) + __builtin_popcount((nw ^ S) & valid);
+        }
+        ups += __builtin_popcount(nw);
+    }
+}
+
+// Convert plane bytes (0 / 1) of global memory to bit words in LDS, or back.
+__device__ __forceinline__ void bits_load(uint32_t* __restrict__ lat, const BatchItem& it, uint32_t Wr) {
+    const uint32_t L = it.L, Hw = it.Hw;
+    const uint32_t words = L * Wr;
+    for (uint32_t w = threadIdx.x; w < 2u * words; w += blockDim.x) {
+        const uint32_t c = w >= words ? 1u : 0u;
+        const uint32_t r = w - c * words;
+        const uint32_t i = r / Wr, k = r - i * Wr;
+        const global_u32* g = as_global(c ? it.p1 : it.p0) + (size_t)i * Hw + 8u * k;
+        uint32_t v = 0;
+        for (uint32_t j = 0; j < 8u && 8u * k + j < Hw; ++j) {
+            // bytes b0..b3 (0 / 1) -> bits 24..27, then to bits 4 j .. 4 j + 3
+            v |= ((g[j] * 0x01020408u) >> 24) << (4u * j);
+        }
+        lat[w] = v;
+    }
+}
+
+__device__ __forceinline__ void bits_store(const uint32_t* __restrict__ lat, const BatchItem& it, uint32_t Wr) {
+    const uint32_t L = it.L, Hw = it.Hw;
+    const uint32_t words = L * Wr;
+    for (uint32_t w = threadIdx.x; w < 2u * words; w += blockDim.x) {
+        const uint32_t c = w >= words ? 1u : 0u;
+        const uint32_t r = w - c * words;
+        const uint32_t i = r / Wr, k = r - i * Wr;
+        global_u32* g = as_global(c ? it.p1 : it.p0) + (size_t)i * Hw + 8u * k;
+        const uint32_t v = lat[w];
+        for (uint32_t j = 0; j < 8u && 8u * k + j < Hw; ++j) {
+            // 4 bits -> bytes 0..3 (bit b to bit 8 b, then keep bit 0 of each byte)
+            g[j] = (((v >> (4u * j)) & 0xfu) * 0x00204081u) & 0x01010101u;
+        }
+    }
+}
+
+// Class thresholds of a bit-packed lattice from its acceptance table (code
+// 8 s + n; an up spin with n up neighbours has m = 4 - n disagreeing).
+__device__ __forceinline__ BitsLattice bits_setup(const BatchItem& it) {
+    BitsLattice bl;
+    bl.L = it.L;
+    bl.Hw = it.Hw;
+    bl.Wr = (it.Hw + 7u) / 8u;
+    const uint32_t H = 4u * it.Hw;
+    bl.hb = (H - 1u) & 31u;
+    bl.last_valid = bl.hb == 31u ? 0xffffffffu : ((1u << (bl.hb + 1u)) - 1u);
+    bl.ferro = it.bits == 1u;
+    const uint32_t ma = bl.ferro ? 1u : 3u, mb = bl.ferro ? 0u : 4u;
+    auto thr64 = [&](uint32_t m) {
+        const uint32_t code = 8u + (4u - m);
+        return ((uint64_t)it.table.thr_hi[code] << 32) | it.table.thr_lo[code];
+    };
+    const uint64_t ta = thr64(ma), tb = thr64(mb);
+    bl.never_a = ta == 0;
+    bl.never_b = tb == 0;
+    bl.thra_m1 = ta == 0 ? 0u : (uint32_t)(ta - 1);
+    bl.thrb_m1 = tb == 0 ? 0u : (uint32_t)(tb - 1);
+    return bl;
+}
+
+// All sweeps of one bit-packed lattice (already in LDS at lat).
+__device__ void run_bits(uint32_t* __restrict__ lat, const BatchItem& it, uint32_t (*part)[kMaxWaves][2]) {
+    const BitsLattice bl = bits_setup(it);
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t nwaves = blockDim.x >> 6;
+    const int64_t N = (int64_t)it.L * it.L;
+    auto flush = [&](uint32_t first, uint32_t count) {
+        if (threadIdx.x < count) {
+            const uint32_t slot = (first + threadIdx.x) % kFlush;
+            int64_t sm = 0, su = 0;
+            for (uint32_t w = 0; w < nwaves; ++w) {
+                sm += part[slot][w][0];
+                su += part[slot][w][1];
+            }
+            // every bond joins colour 0 to colour 1 and was counted once
+            it.series[2 * (first + threadIdx.x)] = 2 * N - 2 * sm;
+            it.series[2 * (first + threadIdx.x) + 1] = 2 * su - N;
+        }
+    };
+    for (uint32_t s = 0; s < it.n; ++s) {
+        const uint32_t t = it.t0 + s;
+        uint32_t mis = 0, ups = 0;
+        bits_pass<false>(lat, bl, 0u, t, it.k0, it.k1, mis, ups);
+        __syncthreads();
+        bits_pass<true>(lat, bl, 1u, t, it.k0, it.k1, mis, ups);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            mis += __shfl_xor(mis, off, 64);
+            ups += __shfl_xor(ups, off, 64);
+        }
+        if (lane == 0) {
+            part[s % kFlush][wv][0] = mis;
+            part[s % kFlush][wv][1] = ups;
+        }
+        __syncthreads();
+        if ((s + 1) % kFlush == 0) flush(s + 1 - kFlush, kFlush);
+    }
+    const uint32_t rem = it.n % kFlush;
+    if (rem) flush(it.n - rem, rem);
+}
+
 }  // namespace
 
 // Run all sweeps of one lattice with its planes at p0/p1 (global memory or
@@ -131,19 +351,27 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __rest
     __shared__ LdsTable lt;
     __shared__ uint32_t s_slot;
     __shared__ uint32_t red[kFlush][kMaxWaves][2];
-    // lattices of at most kBatchLdsBytes run from this LDS copy
-    __shared__ uint32_t lat[kBatchLdsBytes / 4];
+    // the LDS copy of the lattice being swept (bytes or bits)
+    __shared__ uint32_t lat[kBatchBitsLdsBytes / 4];
     const uint32_t count = hdr->count;
     for (;;) {
         if (threadIdx.x == 0) s_slot = atomicAdd(&hdr->head, 1u);
         __syncthreads();
-        const uint32_t slot = s_slot;
+        // the same for every thread: keep it (and the item's fields) scalar
+        const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_slot);
         if (slot >= count) break;
         const BatchItem& it = items[order[slot]];
         load_table(lt, it.table);
         __syncthreads();
         const uint32_t plane_words = it.L * it.Hw;
-        if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
+        const uint32_t bit_words = it.L * ((it.Hw + 7u) / 8u);
+        if (it.bits && 2u * bit_words * 4u <= kBatchBitsLdsBytes && it.n > 0) {
+            bits_load(lat, it, (it.Hw + 7u) / 8u);
+            __syncthreads();
+            run_bits(lat, it, red);
+            __syncthreads();
+            bits_store(lat, it, (it.Hw + 7u) / 8u);
+        } else if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
             uint32_t* l0 = lat;
             uint32_t* l1 = lat + plane_words;
             const global_u32* g0 = as_global(it.p0);
@@ -169,6 +397,26 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __rest
         // everyone has read s_slot and the table before they are replaced
         __syncthreads();
     }
+}
+
+uint32_t bits_mode(const AcceptTable& at) {
+    const uint64_t one = (uint64_t)1 << 32;
+    auto thr = [&](uint32_t code) { return ((uint64_t)at.thr_hi[code] << 32) | at.thr_lo[code]; };
+    uint64_t T[5];
+    for (uint32_t m = 0; m < 5; ++m) {
+        T[m] = thr(8u + (4u - m));    // up spin, 4 - m up neighbours
+        if (thr(m) != T[m]) return 0;  // down spin, m up neighbours
+    }
+    if (T[2] != one) return 0;
+    if (T[3] == one && T[4] == one) return 1;
+    if (T[0] == one && T[1] == one) return 2;
+    return 0;
+}
+
+bool bits_fit(uint32_t L) {
+    if (L % 8u != 0u) return false;
+    const uint64_t wr = (L / 8u + 7u) / 8u;
+    return 2ull * L * wr * 4ull <= kBatchBitsLdsBytes;
 }
 
 uint32_t batch_block_threads() { return kBatchThreads; }

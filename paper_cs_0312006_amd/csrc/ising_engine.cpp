@@ -236,6 +236,8 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         it.k0 = (uint32_t)c->p.seed;
         it.k1 = (uint32_t)(c->p.seed >> 32);
         it.exact = c->exact ? 1u : 0u;
+        it.bits = (!stepped && bits_fit(c->L)) ? bits_mode(c->table) : 0u;
+        it.pad = 0;
         it.table = c->table;
         work[k] = (uint64_t)c->L * c->L * n[k];
         if (n[k]) ++live;

@@ -446,11 +446,13 @@ int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, siz
     bool stepped = plan == ISING_BATCH_STEPPED;
     if (plan == ISING_BATCH_AUTO) {
         // one workgroup per lattice when every lattice is small enough for
-        // a workgroup to sweep it quickly; otherwise spread every lattice
-        // over the whole GPU
-        uint32_t max_l = 0;
-        for (size_t k = 0; k < count; ++k) max_l = std::max(max_l, ctxs[k]->L);
-        stepped = max_l > kResidentBatchMaxL;
+        // a workgroup to sweep it quickly, or runs bit-packed from its LDS;
+        // otherwise spread every lattice over the whole GPU
+        stepped = false;
+        for (size_t k = 0; k < count; ++k) {
+            const ising_ctx* c = ctxs[k];
+            if (c->L > kResidentBatchMaxL && !(bits_fit(c->L) && bits_mode(c->table) != 0)) stepped = true;
+        }
     }
     return engine_run(ctxs, n_sweeps, count, stream ? (hipStream_t)stream : ctxs[0]->stream, stepped);
 }

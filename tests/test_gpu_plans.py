@@ -120,6 +120,34 @@ def test_batch_equals_solo_and_oracle(b, o, plan):
         G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref, f"batch L={r.L}")
 
 
+def test_batch_bit_packed_couplings_and_sides(b, o):
+    """The resident batch's bit-packed path (h = 0, side up to 1072): J > 0,
+    J < 0 and J = 0, thresholds of 0 (T = 0.05), near 1 (T = 50) and at T_c,
+    sides with partial 32-site words (8, 24, 40, 136), the largest sides that
+    fit local memory (1072, 1080) and one that does not (1088, swept in
+    global memory), in one batch call: each result equals the oracle's run
+    of that lattice alone."""
+    runs = [W.Run(L=8, J=1.0, T=2.269185, seed=1, p_up=0.5, sweeps=40),
+            W.Run(L=24, J=-1.0, T=2.0, seed=2, p_up=0.5, sweeps=30),
+            W.Run(L=40, J=1.0, T=0.05, seed=3, p_up=0.5, sweeps=20),
+            W.Run(L=136, J=-2.0, T=0.3, seed=4, p_up=0.5, sweeps=20),
+            W.Run(L=64, J=0.0, T=1.0, seed=5, p_up=0.5, sweeps=10),
+            W.Run(L=96, J=0.5, T=50.0, seed=6, p_up=1.0, sweeps=10),
+            W.Run(L=1072, J=1.0, T=2.269185, seed=7, p_up=0.5, sweeps=6),
+            W.Run(L=1080, J=-1.0, T=1.5, seed=8, p_up=1.0, sweeps=4),
+            W.Run(L=1088, J=1.0, T=3.0, seed=9, p_up=0.5, sweeps=3)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    G.log("bit-packed batch of 9 (RESIDENT)")
+    b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], b.ISING_BATCH_RESIDENT)
+    for r, ctx in zip(runs, ctxs):
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        spins = b.ising_copy_spins(ctx, r.L)
+        b.ising_destroy(ctx)
+        G.log(f"bit-packed batch: L={r.L} J={r.J} T={r.T} vs oracle")
+        G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r),
+                      f"bit-packed L={r.L} J={r.J} T={r.T}")
+
+
 def test_batch_rejects_before_launching(b):
     good = b.ising_create(16)
     bad = b.ising_create(10)  # L % 8 != 0
