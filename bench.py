@@ -582,11 +582,14 @@ def main():
             extra.append({"h": r.h, "p_up": r.p_up, "sweeps": steps,
                           "value": r.L * r.L * steps / h["ms"] / 1e6, "unit": "attempts/ns"})
         out["c2_other_runs"] = extra
-        stepped, h_st = run_batched(b, torch, stream, 1024, args.batched_sweeps, args.batched_sample, plan=2)
-        resident, h_re = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=1)
-        stepped["resident_plan_same_config"] = {"value": resident["value"], "ms": resident["ms"],
-                                                "results_identical": h_st == h_re}
-        out["batched"] = stepped
+        # the plan ISING_BATCH_AUTO picks: resident, every lattice of this
+        # configuration (h = 0, L <= 1024) held bit-packed in workgroup memory
+        auto, h_au = run_batched(b, torch, stream, 1024, args.batched_sweeps, args.batched_sample, plan=0)
+        auto["plan"] = "auto: resident, lattices bit-packed in workgroup memory"
+        stepped, h_st = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=2)
+        auto["stepped_plan_same_config"] = {"value": stepped["value"], "ms": stepped["ms"],
+                                            "results_identical": h_st == h_au}
+        out["batched"] = auto
 
     if not args.no_extra and not args.no_served:
         out["served"] = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)

@@ -194,21 +194,25 @@ __device__ __forceinline__ void bits_pass(uint32_t* __restrict__ lat, const Bits
     const uint32_t kn = last ? 0u : k + 1;       // next word of the row (wrapping)
     const uint32_t kp = k == 0 ? Wr - 1 : k - 1;  // previous word of the row (wrapping)
     const uint32_t top_p = k == 0 ? bl.hb : 31u;  // last valid bit of the previous word
-    for (uint32_t i = tid / Wr; i < L; i += rs) {
-        const uint32_t iu = i == 0 ? L - 1 : i - 1;
-        const uint32_t id = i + 1 == L ? 0 : i + 1;
-        const uint32_t own = own_p[i * Wr + k];
-        const uint32_t U = oth_p[iu * Wr + k];
-        const uint32_t D = oth_p[id * Wr + k];
-        const uint32_t O = oth_p[i * Wr + k];
-        const uint32_t On = oth_p[i * Wr + kn];
-        const uint32_t Op = oth_p[i * Wr + kp];
+    // row i's word offset, and its first quad, stepped rather than multiplied
+    uint32_t i = tid / Wr;
+    uint32_t ro = i * Wr, q0 = i * Hw + 8u * k;
+    const uint32_t ro_step = rs * Wr, q_step = rs * Hw, wrap = L * Wr;
+    for (; i < L; i += rs, ro += ro_step, q0 += q_step) {
+        const uint32_t rou = i == 0 ? wrap - Wr : ro - Wr;
+        const uint32_t rod = i + 1 == L ? 0u : ro + Wr;
+        const uint32_t own = own_p[ro + k];
+        const uint32_t U = oth_p[rou + k];
+        const uint32_t D = oth_p[rod + k];
+        const uint32_t O = oth_p[ro + k];
+        const uint32_t On = oth_p[ro + kn];
+        const uint32_t Op = oth_p[ro + kp];
         // same-row neighbour of site m: m + 1 when (i + c) is odd, else m - 1
         const uint32_t s_up = (O >> 1) | ((On & 1u) << top);
         const uint32_t s_dn = ((O << 1) | ((Op >> top_p) & 1u)) & valid;
         const uint32_t S = ((i + c) & 1u) ? s_up : s_dn;
         uint32_t ra, rb;
-        bits_compares(i * Hw + 8u * k, t, c, k0, k1, bl.thra_m1, bl.thrb_m1, ra, rb);
+        bits_compares(q0, t, c, k0, k1, bl.thra_m1, bl.thrb_m1, ra, rb);
         if (bl.never_a) ra = 0xffffffffu;
         if (bl.never_b) rb = 0xffffffffu;
         // disagreement masks and the two classes
@@ -225,11 +229,12 @@ __device__ __forceinline__ void bits_pass(uint32_t* __restrict__ lat, const Bits
         }
         const uint32_t reject = (ea & ra) | (eb & rb);
         const uint32_t nw = own ^ (valid & ~reject);
-        own_p[i * Wr + k] = nw;
+        own_p[ro + k] = nw;
         if (OBS) {
-            // bonds of this colour-1 word, all final now, that disagree
-            mis += __builtin_popcount((nw ^ U) & valid) + __builtin_popcount((nw ^ D) & valid) +
-                   __builtin_popcount((nw ^ O) & valid) + __builtin_popcount((nw ^ S) & valid);
+            // bonds of this colour-1 word, all final now, that disagree (bits
+            // past the row's end are zero in every operand)
+            mis += __builtin_popcount(nw ^ U) + __builtin_popcount(nw ^ D) + __builtin_popcount(nw ^ O) +
+                   __builtin_popcount(nw ^ S);
         }
         ups += __builtin_popcount(nw);
     }
