@@ -177,9 +177,12 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
  *   with h = 0 and side up to 1072 is held in the workgroup's local memory
  *   at one bit per site for all its sweeps; other lattices of side up to 256
  *   are held there as bytes; larger ones are swept in global memory;
- * ISING_BATCH_STEPPED: every colour pass is one launch over the chunks of
- *   all lattices, so each lattice is spread over the whole GPU; sweeps are
- *   replayed from a captured graph in groups of 16;
+ * ISING_BATCH_STEPPED: every sweep is one launch over the tiles of all
+ *   lattices, so each lattice is spread over the whole GPU; sweeps are
+ *   replayed from a captured graph in groups of 16. When every side is a
+ *   multiple of 16 the sweep is one pass (each lattice alternates between
+ *   two buffers; a context without its second buffer gets one, L*L bytes,
+ *   on first use); otherwise it is a launch per colour, in place;
  * ISING_BATCH_AUTO: resident when every lattice is held in local memory
  *   (side <= 256, or h = 0 and side <= 1072), else stepped.
  * Results are identical for every plan. */

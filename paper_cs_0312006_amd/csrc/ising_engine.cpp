@@ -1,5 +1,7 @@
 // Batch engine: runs many contexts' sweeps as one persistent, workgroup-
-// resident launch (ising_batch.hip), replayed from a captured hipGraph.
+// resident launch (ising_batch.hip), or as stepped sweeps over the tiles of
+// every lattice (ising_multi_fused.hip, ising_multi.hip), replayed from
+// captured hipGraphs.
 //
 // Per device the engine owns a device array of lattice descriptors, the
 // queue order and a header, plus pinned host copies used to stage them. A
@@ -58,6 +60,9 @@ struct Engine {
     hipGraph_t mgraph = nullptr;
     hipGraphExec_t mexec = nullptr;
     uint32_t mgrid = 0;
+    // stepped plan, fused walk (sides multiple of 16)
+    hipGraph_t fgraph = nullptr;
+    hipGraphExec_t fexec = nullptr;
 };
 
 constexpr uint32_t kSweepsPerReplay = 16;
@@ -74,6 +79,10 @@ void release_buffers(Engine& e) {
     if (e.mgraph) (void)hipGraphDestroy(e.mgraph);
     e.mexec = nullptr;
     e.mgraph = nullptr;
+    if (e.fexec) (void)hipGraphExecDestroy(e.fexec);
+    if (e.fgraph) (void)hipGraphDestroy(e.fgraph);
+    e.fexec = nullptr;
+    e.fgraph = nullptr;
     if (e.d_stage) (void)hipFree(e.d_stage);
     if (e.h_stage) (void)hipHostFree(e.h_stage);
     e.d_stage = nullptr;
@@ -189,6 +198,23 @@ hipError_t ensure_multi_graph(Engine& e) {
     return r;
 }
 
+// Capture G sweeps of the stepped plan's fused walk (one advance node + G launches).
+hipError_t ensure_fused_graph(Engine& e) {
+    if (e.fexec) return hipSuccess;
+    hipStream_t cap = nullptr;
+    hipError_t r = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (r != hipSuccess) return r;
+    r = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (r == hipSuccess) {
+        hipError_t lr = launch_multi_fused_graph_body(e.d_items, e.d_vbs, e.d_mhdr, kSweepsPerReplay, e.mgrid, cap);
+        r = hipStreamEndCapture(cap, &e.fgraph);
+        if (lr != hipSuccess) r = lr;
+    }
+    if (r == hipSuccess) r = hipGraphInstantiate(&e.fexec, e.fgraph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    return r;
+}
+
 }  // namespace
 
 int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped) {
@@ -216,6 +242,21 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
             return ctx_fail(ctxs[0], r, "engine: staging wait");
         e.staged_pending = false;
     }
+    // the stepped plan walks sides that are multiples of 16 with the fused
+    // one-pass kernel, each lattice ping-ponging between its two buffers
+    bool fused = stepped;
+    for (size_t k = 0; fused && k < count; ++k) fused = multi_fused_supported(ctxs[k]->L);
+    if (fused) {
+        for (size_t k = 0; k < count; ++k) {
+            ising_ctx* c = ctxs[k];
+            if (c->buf[1] || n[k] == 0) continue;
+            if (hipMalloc(&c->buf[1], (size_t)c->L * c->L) != hipSuccess) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
+            }
+            c->owns_buf[1] = true;
+        }
+    }
     std::vector<uint64_t> work(count);
     uint32_t live = 0;
     for (size_t k = 0; k < count; ++k) {
@@ -224,6 +265,13 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         BatchItem& it = e.h_items[k];
         it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
         it.p1 = reinterpret_cast<uint32_t*>(pl.p[1]);
+        it.q0 = nullptr;
+        it.q1 = nullptr;
+        if (fused && c->buf[1]) {
+            const Planes alt = ctx_planes_alt(c);
+            it.q0 = reinterpret_cast<uint32_t*>(alt.p[0]);
+            it.q1 = reinterpret_cast<uint32_t*>(alt.p[1]);
+        }
         it.series = c->series + 2 * c->series_len;
         it.L = c->L;
         it.Hw = c->L / 8u;
@@ -257,7 +305,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         uint64_t vb = 0;
         for (size_t k = 0; k < count; ++k) {
             e.h_vbs[k] = (uint32_t)vb;
-            vb += multi_vblocks(e.h_items[k].L, e.h_items[k].cw);
+            vb += fused ? multi_fused_tiles(e.h_items[k].L) : multi_vblocks(e.h_items[k].L, e.h_items[k].cw);
         }
         if (vb >= ((uint64_t)1 << 32)) return ISING_ERANGE;
         e.h_vbs[count] = (uint32_t)vb;
@@ -287,6 +335,12 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     if (!stepped) {
         r = ensure_graph(e, s);
         if (r == hipSuccess) r = hipGraphLaunch(e.exec, s);
+    } else if (fused) {
+        // the sweeps add their tiles' (B, M) into series slots cleared here
+        r = launch_multi_fused_clear(e.d_items, (uint32_t)count, s);
+        if (r == hipSuccess) r = ensure_fused_graph(e);
+        const uint64_t replays = (max_n + kSweepsPerReplay - 1) / kSweepsPerReplay;
+        for (uint64_t k = 0; r == hipSuccess && k < replays; ++k) r = hipGraphLaunch(e.fexec, s);
     } else {
         r = ensure_multi_graph(e);
         const uint64_t replays = (max_n + kSweepsPerReplay - 1) / kSweepsPerReplay;
@@ -307,6 +361,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     for (size_t k = 0; k < count; ++k) {
         ctxs[k]->t += n[k];
         ctxs[k]->series_len += n[k];
+        if (fused && (n[k] & 1u)) ctxs[k]->cur ^= 1;  // an odd number of ping-pong sweeps
     }
     return ISING_OK;
 }

@@ -25,112 +25,12 @@
 #include <stdint.h>
 
 #include "ising_device.hpp"
+#include "ising_fused_core.hpp"
 #include "ising_launch.hpp"
 
 namespace ising {
 
 namespace {
-
-// DPP controls (GFX9): whole-wave shift by one lane.
-constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l+1
-constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l-1
-
-// lane l gets v of lane l+1; lane 63 gets `edge`.
-__device__ __forceinline__ uint32_t from_right(uint32_t v, uint32_t edge) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShl1, 0xf, 0xf, false);
-}
-// lane l gets v of lane l-1; lane 0 gets `edge`.
-__device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShr1, 0xf, 0xf, false);
-}
-
-template <int CW>
-struct Row {
-    uint32_t v[CW];
-};
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-// Raw buffer over a whole plane; word 3 is the gfx9 resource format for
-// untyped 32-bit data.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const uint32_t* p) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(p), 0, -1, 0x00020000);
-}
-
-// CW words at byte offset xb (lane) + soff (row, uniform) of a plane.
-template <int CW>
-__device__ __forceinline__ Row<CW> ld(__amdgpu_buffer_rsrc_t rs, uint32_t xb, uint32_t soff) {
-    Row<CW> r;
-    if constexpr (CW == 4) {
-        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, xb, soff, 0);
-        r.v[0] = v.x; r.v[1] = v.y; r.v[2] = v.z; r.v[3] = v.w;
-    } else if constexpr (CW == 2) {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, xb, soff, 0);
-        r.v[0] = v.x; r.v[1] = v.y;
-    } else {
-        r.v[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, xb, soff, 0);
-    }
-    return r;
-}
-
-// CW words to byte offset off of a plane. The whole offset is in the vector
-// operand and the scalar offset is the constant 0: a store wider than 64
-// bits reads part of its data registers after issue, and with a register in
-// the scalar offset field the compiler does not keep the next instructions
-// from overwriting them (seen on gfx950 as wrong words in the last lanes of
-// each group of 16); with a constant there it does.
-template <int CW>
-__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t rs, uint32_t off, const Row<CW>& r) {
-    if constexpr (CW == 4) {
-        const u32x4 v = {r.v[0], r.v[1], r.v[2], r.v[3]};
-        __builtin_amdgcn_raw_buffer_store_b128(v, rs, off, 0, 0);
-    } else if constexpr (CW == 2) {
-        const u32x2 v = {r.v[0], r.v[1]};
-        __builtin_amdgcn_raw_buffer_store_b64(v, rs, off, 0, 0);
-    } else {
-        __builtin_amdgcn_raw_buffer_store_b32(r.v[0], rs, off, 0, 0);
-    }
-}
-
-// Update one lane's CW words of a plane row. P = (i + c) & 1 selects the
-// same-row neighbour side; `edge` is the word just outside the tile on that
-// side (right for P == 1, left for P == 0) of the `same` row. Word w's draw
-// counter is q = (row offset) + xw[w]; m0row = M0 * (row offset), so the
-// first Philox product M0 * q is one multiply-add per word.
-template <int CW, bool EXACT, int P, bool OBS>
-__device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>& own, const Row<CW>& up,
-                                              const Row<CW>& dn, const Row<CW>& same, uint32_t edge,
-                                              const Row<CW>& xw, uint64_t m0row, uint32_t t, uint32_t c,
-                                              uint32_t k0, uint32_t k1, uint32_t& sad) {
-    const uint32_t nb = P ? from_right(same.v[0], edge) : from_left(same.v[CW - 1], edge);
-    Row<CW> out;
-#pragma unroll
-    for (int w = 0; w < CW; ++w) {
-        uint32_t S;
-        if (P) {
-            const uint32_t nxt = (w + 1 < CW) ? same.v[(w + 1 < CW) ? w + 1 : 0] : nb;
-            S = __builtin_amdgcn_alignbyte(nxt, same.v[w], 1);
-        } else {
-            const uint32_t prv = (w > 0) ? same.v[(w > 0) ? w - 1 : 0] : nb;
-            S = __builtin_amdgcn_alignbyte(same.v[w], prv, 3);
-        }
-        // table offset 4 (8 s + n) = ((8 s + three neighbours) + fourth) << 2:
-        // add3, shift-add, add-shift
-        const uint32_t t3 = up.v[w] + dn.v[w] + S;
-        const uint32_t code4 = (((own.v[w] << 3) + t3) + same.v[w]) << 2;
-        const uint32_t n4 = (t3 + same.v[w]) << 2;  // 4 n per byte (colour-1 observables only)
-        const uint4 r = philox_p0((uint64_t)kPhiloxM0 * xw.v[w] + m0row, t, c, 0u, k0, k1);
-        const uint32_t Wn = own.v[w] ^ flip_mask_code<EXACT>(lt, code4, r);
-        out.v[w] = Wn;
-        if (OBS) sad = sad_misaligned4(Wn, n4, sad);
-    }
-    return out;
-}
-
-__device__ __forceinline__ uint32_t wrap_row(int i, uint32_t L) {
-    return (uint32_t)(i < 0 ? i + (int)L : (i >= (int)L ? i - (int)L : i));
-}
 
 __device__ __forceinline__ uint32_t xcd_block_f(uint32_t nblocks) {
     const uint32_t b = blockIdx.x;

@@ -94,6 +94,8 @@ hipError_t launch_reduce_partials(const PartialReduce& red, hipStream_t s);
 struct BatchItem {
     uint32_t* p0;       // colour planes, updated in place
     uint32_t* p1;
+    uint32_t* q0;       // the other buffer's planes (stepped fused plan: ping-pong)
+    uint32_t* q1;
     int64_t* series;    // 2 int64 per sweep, for sweeps t0 .. t0+n-1
     uint32_t L, Hw, cw, t0, n, k0, k1, exact;
     uint32_t bits;      // resident batch: 1 / 2 = bit-packed in LDS (see bits_mode), 0 = not
@@ -137,6 +139,17 @@ constexpr uint32_t kMultiChunksPerThread = 4;
 uint32_t multi_vblocks(uint32_t L, uint32_t cw);
 hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_start, MultiHeader* hdr,
                                    uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
+
+// Stepped multi-lattice sweeps with the fused walk (ising_multi_fused.hip):
+// one launch per sweep over the tiles (kMultiFusedRows rows by 128 words) of
+// every item, each lattice ping-ponging between p and q; vb_start[k] is item
+// k's first tile. Sides must satisfy L % 16 == 0.
+constexpr uint32_t kMultiFusedRows = 32;
+bool multi_fused_supported(uint32_t L);
+uint32_t multi_fused_tiles(uint32_t L);
+hipError_t launch_multi_fused_clear(const BatchItem* items, uint32_t n_items, hipStream_t s);
+hipError_t launch_multi_fused_graph_body(const BatchItem* items, const uint32_t* tile_start, MultiHeader* hdr,
+                                         uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
 
 // Creutz demon dynamics (ising_creutz.hip): dm holds the demon planes, in
 // the spin planes' layout. A sweep is two in-place passes; the word path

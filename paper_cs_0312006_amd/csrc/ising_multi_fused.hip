@@ -1,0 +1,245 @@
+// Stepped multi-lattice sweeps with the fused one-pass walk: one launch per
+// sweep covers the tiles of every lattice in a work list, so each lattice,
+// small or large, is spread over the whole GPU and crosses HBM once per
+// sweep (2 bytes per site update, against 3 for a pass per colour).
+//
+// Each lattice ping-pongs between its two buffers: sweep s of a call reads
+// buffer s & 1 of the item (p = the current lattice, q = the other one) and
+// writes the other. A wave walks one tile of up to 32 rows by 128 words of
+// a plane row (two words per lane), exactly as the single-lattice fused
+// kernel does, with two differences:
+//   - tiles at a lattice's right and bottom edges may be narrower and
+//     shorter: lanes past the lattice's last word shadow its last lane
+//     (their loads stay in range, nothing of theirs is stored or counted),
+//     and that lane takes its right neighbour from the edge word;
+//   - the per-sweep (B, M) of a lattice are summed over its tiles with 64-bit
+//     atomic adds into its series slot, which is cleared before the sweeps.
+// The draws are keyed by (seed, sweep, colour, site) as everywhere else, so
+// the result is the same as any other schedule of the same sweeps.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ising_device.hpp"
+#include "ising_fused_core.hpp"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t kMfThreads = 256;
+constexpr int kMfCW = 2;  // words per lane
+constexpr uint32_t kMfTileWords = 64u * kMfCW;
+
+__device__ __forceinline__ uint32_t wrap_row_m(int i, uint32_t L) {
+    return (uint32_t)(i < 0 ? i + (int)L : (i >= (int)L ? i - (int)L : i));
+}
+
+// Partial (B, M) of one tile of item `it` for its sweep `s` of this call.
+template <bool EXACT>
+__device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it, uint32_t tx, uint32_t ty,
+                                        uint32_t s, int64_t& b_out, int64_t& m_out) {
+    constexpr int CW = kMfCW;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t L = it.L, Hw = it.Hw, k0 = it.k0, k1 = it.k1;
+    const uint32_t t = it.t0 + s;
+    const uint32_t X0 = tx * kMfTileWords;
+    const uint32_t wds = min(kMfTileWords, Hw - X0);  // words of the lattice in this tile
+    const uint32_t la = wds / CW - 1u;                 // last lane holding lattice words
+    const bool active = lane <= la;
+    const bool is_last = lane == la;
+    const uint32_t x = X0 + min(lane, la) * CW;
+    const int r0 = (int)(ty * kMultiFusedRows);
+    const int R = (int)min(kMultiFusedRows, L - ty * kMultiFusedRows);  // 16 or 32 rows (L % 16 == 0)
+    const uint32_t xl = X0 == 0 ? Hw - 1 : X0 - 1;
+    const uint32_t xr = X0 + wds == Hw ? 0u : X0 + wds;
+    const bool odd = (s & 1u) != 0u;
+    const uint32_t* __restrict__ s0 = odd ? it.q0 : it.p0;
+    const uint32_t* __restrict__ s1 = odd ? it.q1 : it.p1;
+    uint32_t* __restrict__ d0 = odd ? it.p0 : it.q0;
+    uint32_t* __restrict__ d1 = odd ? it.p1 : it.q1;
+
+    auto row_ptr = [&](const uint32_t* base, int i) { return base + (size_t)wrap_row_m(i, L) * Hw; };
+
+    // old colour-1 word just outside the tile for the colour-0 update of row
+    // r0 + 1 + lane, and the new colour-0 word just outside it for row
+    // r0 + lane (see the single-lattice kernel)
+    uint32_t edge_c1 = 0;
+    if (lane < (uint32_t)R) {
+        const int j = r0 + 1 + (int)lane;
+        const uint32_t rj = wrap_row_m(j, L);
+        edge_c1 = row_ptr(s1, j)[(rj & 1u) ? xr : xl];
+    }
+    uint32_t edge_c0 = 0;
+    if (lane < (uint32_t)R) {
+        const int i = r0 + (int)lane;
+        const uint32_t ri = wrap_row_m(i, L);
+        const uint32_t xe = (ri & 1u) ? xl : xr;
+        const uint32_t pe = ri & 1u;
+        const uint32_t xn = pe ? (xe + 1 == Hw ? 0u : xe + 1) : (xe == 0 ? Hw - 1 : xe - 1);
+        const uint32_t own = row_ptr(s0, i)[xe];
+        const uint32_t up = row_ptr(s1, i - 1)[xe];
+        const uint32_t dn = row_ptr(s1, i + 1)[xe];
+        const uint32_t same = row_ptr(s1, i)[xe];
+        const uint32_t nbw = row_ptr(s1, i)[xn];
+        const uint32_t S = pe ? __builtin_amdgcn_alignbyte(nbw, same, 1) : __builtin_amdgcn_alignbyte(same, nbw, 3);
+        const uint32_t n = up + dn + same + S;
+        const uint4 r = philox(ri * Hw + xe, t, 0u, 0u, k0, k1);
+        edge_c0 = own ^ flip_mask<EXACT>(lt, own, n, r);
+    }
+
+    uint32_t sad = 0, ups = 0, ups8 = 0, dummy = 0;
+    const uint32_t xb = x * 4u;
+    Row<CW> xw;
+#pragma unroll
+    for (int w = 0; w < CW; ++w) xw.v[w] = x + (uint32_t)w;
+    const __amdgpu_buffer_rsrc_t rs0 = plane_rsrc(s0), rs1 = plane_rsrc(s1);
+    const __amdgpu_buffer_rsrc_t rd0 = plane_rsrc(d0), rd1 = plane_rsrc(d1);
+    auto rword = [&](int i) { return wrap_row_m(i, L) * Hw; };
+    auto rbyte = [&](int i) { return rword(i) * 4u; };
+    auto m0row = [&](int i) { return (uint64_t)kPhiloxM0 * rword(i); };
+    Row<CW> c1[4], c0o[2], c0n[4];
+    const Row<CW> c1m2 = ld<CW>(rs1, xb, rbyte(r0 - 2));
+    const Row<CW> c1m1 = ld<CW>(rs1, xb, rbyte(r0 - 1));
+    c1[0] = ld<CW>(rs1, xb, rbyte(r0));
+    c1[1] = ld<CW>(rs1, xb, rbyte(r0 + 1));
+    c1[2] = ld<CW>(rs1, xb, rbyte(r0 + 2));
+    const Row<CW> c0om1 = ld<CW>(rs0, xb, rbyte(r0 - 1));
+    c0o[0] = ld<CW>(rs0, xb, rbyte(r0));
+    c0o[1] = ld<CW>(rs0, xb, rbyte(r0 + 1));
+    const uint32_t eR = row_ptr(s1, r0 - 1)[xr];
+    const uint32_t eL = row_ptr(s1, r0)[xl];
+    c0n[0] = update_row<CW, EXACT, 1, false, true>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, m0row(r0 - 1), t, 0u, k0,
+                                                   k1, dummy, is_last);
+    c0n[1] = update_row<CW, EXACT, 0, false, true>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, m0row(r0), t, 0u, k0,
+                                                   k1, dummy, is_last);
+    if (active) st<CW>(rd0, xb + rbyte(r0), c0n[1]);
+
+#pragma unroll 1
+    for (int k = 0; k < R; k += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = r0 + k + u;
+            c1[(u + 3) & 3] = ld<CW>(rs1, xb, rbyte(i + 3));
+            c0o[u & 1] = ld<CW>(rs0, xb, rbyte(i + 2));
+            const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c1, k + u);
+            const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c0, k + u);
+            const uint64_t m1 = m0row(i + 1);
+            const uint64_t m0 = m0row(i);
+            Row<CW> c1n;
+            if ((u & 1) == 0) {
+                c0n[(u + 2) & 3] =
+                    update_row<CW, EXACT, 1, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                                                          c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy, is_last);
+                c1n = update_row<CW, EXACT, 1, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                                                           c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad, is_last);
+            } else {
+                c0n[(u + 2) & 3] =
+                    update_row<CW, EXACT, 0, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                                                          c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy, is_last);
+                c1n = update_row<CW, EXACT, 0, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                                                           c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad, is_last);
+            }
+            if (active) {
+                if (k + u + 1 < R) st<CW>(rd0, xb + rbyte(i + 1), c0n[(u + 2) & 3]);
+                st<CW>(rd1, xb + rbyte(i), c1n);
+            }
+#pragma unroll
+            for (int w = 0; w < CW; ++w) ups8 += c1n.v[w] + c0n[(u + 1) & 3].v[w];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        ups = __builtin_amdgcn_sad_u8(ups8, 0u, ups);
+        ups8 = 0;
+    }
+
+    // partials of the lanes that hold lattice words: B = 16 * words - 2 *
+    // (sad / 4), M = 2 * ups - 8 * words
+    const int64_t words = active ? (int64_t)R * CW : 0;
+    int64_t b = active ? 16 * words - (int64_t)(sad >> 1) : 0;
+    int64_t m = active ? 2 * (int64_t)ups - 8 * words : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        b += __shfl_xor(b, off, 64);
+        m += __shfl_xor(m, off, 64);
+    }
+    b_out = b;
+    m_out = m;
+}
+
+}  // namespace
+
+// Sweep hdr->s_base + s of every item with that sweep pending. Waves take
+// virtual tiles (tile_start[k] = item k's first) in a grid-stride loop.
+__global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __restrict__ items,
+                                                            const uint32_t* __restrict__ tile_start,
+                                                            const MultiHeader* __restrict__ hdr, uint32_t s) {
+    __shared__ LdsTable lt[kMfThreads / 64];
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t n_items = hdr->n_items, total = hdr->total_vblocks;
+    const uint32_t sweep = hdr->s_base + s;
+    const uint32_t waves = gridDim.x * (kMfThreads / 64);
+    for (uint32_t g0 = blockIdx.x * (kMfThreads / 64) + wv; g0 < total; g0 += waves) {
+        const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
+        uint32_t lo = 0, hi = n_items;  // last item whose first tile is <= g
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tile_start[mid] <= g) lo = mid;
+            else hi = mid;
+        }
+        const BatchItem& it = items[lo];
+        if (sweep >= it.n) continue;  // this lattice is done: the whole wave skips
+        // this wave's copy of the item's acceptance table
+        if (lane < 16) {
+            lt[wv].t32[lane] = it.table.thr_m1[lane];
+            lt[wv].t64[lane] = make_uint2(it.table.thr_lo[lane], it.table.thr_hi[lane]);
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t n_tx = (it.Hw + kMfTileWords - 1) / kMfTileWords;
+        const uint32_t tile = g - tile_start[lo];
+        const uint32_t tx = tile % n_tx, ty = tile / n_tx;
+        int64_t b, m;
+        if (it.exact) mf_tile<true>(lt[wv], it, tx, ty, sweep, b, m);
+        else mf_tile<false>(lt[wv], it, tx, ty, sweep, b, m);
+        if (lane == 0) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep]), (unsigned long long)b);
+            atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep + 1]), (unsigned long long)m);
+        }
+        // the next tile's table must not overwrite this one while lanes read it
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Clear the series slots item k's sweeps of this call will add into.
+__global__ void __launch_bounds__(256) k_multi_fused_clear(const BatchItem* __restrict__ items, uint32_t n_items) {
+    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+        const BatchItem& it = items[k];
+        for (uint32_t j = threadIdx.x; j < 2u * it.n; j += blockDim.x) it.series[j] = 0;
+    }
+}
+
+bool multi_fused_supported(uint32_t L) { return L % 16u == 0u && L >= 16u; }
+
+uint32_t multi_fused_tiles(uint32_t L) {
+    const uint32_t Hw = L / 8u;
+    return ((Hw + kMfTileWords - 1) / kMfTileWords) * ((L + kMultiFusedRows - 1) / kMultiFusedRows);
+}
+
+hipError_t launch_multi_fused_clear(const BatchItem* items, uint32_t n_items, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    k_multi_fused_clear<<<min(n_items, 1024u), 256, 0, s>>>(items, n_items);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(64) k_multi_fused_advance(MultiHeader* hdr, uint32_t g) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) hdr->s_base += g;
+}
+
+hipError_t launch_multi_fused_graph_body(const BatchItem* items, const uint32_t* tile_start, MultiHeader* hdr,
+                                         uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s) {
+    k_multi_fused_advance<<<1, 64, 0, s>>>(hdr, sweeps_per_replay);
+    for (uint32_t k = 0; k < sweeps_per_replay; ++k)
+        k_multi_fused<<<grid, kMfThreads, 0, s>>>(items, tile_start, hdr, k);
+    return hipGetLastError();
+}
+
+}  // namespace ising

@@ -148,6 +148,37 @@ def test_batch_bit_packed_couplings_and_sides(b, o):
                       f"bit-packed L={r.L} J={r.J} T={r.T}")
 
 
+def test_batch_stepped_fused_walk_ragged_tiles(b, o):
+    """The stepped plan's one-pass walk (every side a multiple of 16): sides
+    whose tiles end before the last lane (plane rows of 2 to 258 words) and
+    after 16 of 32 rows, h = 0 and h != 0, J < 0, thresholds of 0 (T = 0.2),
+    odd and even sweep counts (each lattice alternates between two buffers),
+    and a second call that continues the first: every result equals the
+    oracle's run of that lattice alone."""
+    runs = [W.Run(L=16, J=1.0, h=0.0, T=2.269185, seed=1, p_up=0.5, sweeps=7),
+            W.Run(L=48, J=1.0, h=0.1, T=1.8, seed=2, p_up=1.0, sweeps=12),
+            W.Run(L=80, J=-1.0, h=0.05, T=2.5, seed=3, p_up=0.5, sweeps=9),
+            W.Run(L=144, J=1.0, h=0.0, T=0.2, seed=4, p_up=0.5, sweeps=10),
+            W.Run(L=272, J=0.7, h=-0.2, T=3.0, seed=5, p_up=0.5, sweeps=5),
+            W.Run(L=1040, J=1.0, h=0.0, T=2.269185, seed=6, p_up=0.5, sweeps=3),
+            W.Run(L=2064, J=1.0, h=0.05, T=2.0, seed=7, p_up=0.5, sweeps=2),
+            W.Run(L=512, J=1.0, h=0.0, T=2.269185, seed=8, p_up=0.5, sweeps=0)]
+    extra = [4, 1, 6, 3, 2, 1, 1, 3]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    G.log("stepped fused walk: first call")
+    b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], b.ISING_BATCH_STEPPED)
+    G.log("stepped fused walk: second call")
+    b.ising_sweep_batch_plan(ctxs, extra, b.ISING_BATCH_STEPPED)
+    for r, ctx, e in zip(runs, ctxs, extra):
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        spins = b.ising_copy_spins(ctx, r.L)
+        b.ising_destroy(ctx)
+        G.log(f"stepped fused walk: L={r.L} vs oracle")
+        assert obs.sweeps_done == r.sweeps + e
+        G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash},
+                      G.oracle_run(o, r, sweeps=r.sweeps + e), f"stepped fused L={r.L}")
+
+
 def test_batch_rejects_before_launching(b):
     good = b.ising_create(16)
     bad = b.ising_create(10)  # L % 8 != 0
