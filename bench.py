@@ -243,10 +243,13 @@ def run_served(rates, count, epoch_sweeps):
     from paper_cs_0312006_amd import serve
     from paper_cs_0312006_amd import workloads as W
     out = []
-    ex = serve.GpuExecutor(hash_results=False)
     for rate in [float(x) for x in rates.split(",") if x]:
-        reqs = W.request_stream(rate, count=count)
-        res, stats = serve.serve(reqs, ex, epoch_sweeps=epoch_sweeps)
+        ex = serve.GpuExecutor(hash_results=False)
+        try:
+            reqs = W.request_stream(rate, count=count)
+            res, stats = serve.serve(reqs, ex, epoch_sweeps=epoch_sweeps)
+        finally:
+            ex.close()
         s = serve.summarize(res, stats["makespan_s"])
         s.update({"rate_per_s": rate, "epochs": stats["epochs"], "epoch_sweeps": epoch_sweeps,
                   "offered_attempts_per_ns": rate * sum(r.run.attempts() for r in reqs) / len(reqs) / 1e9})

@@ -250,6 +250,24 @@ int ising_demon_sum(ising_ctx* ctx, int64_t* out);
  * row-major layout. Synchronises. */
 int ising_copy_demons(ising_ctx* ctx, uint8_t* host, size_t n);
 
+/* Re-initialise a context for new parameters of the same side, keeping its
+ * device buffers (a request server reusing contexts instead of freeing and
+ * allocating, which would synchronise the device): the result is the same
+ * as ising_create with *params, i.e. the acceptance table of (J, h, T), the
+ * initial lattice drawn from (seed, p_up) (Section 2.2), sweep index 0 and
+ * an empty series. params->L must equal the context's side; the plan is
+ * kept (params->flags must be ISING_PLAN_AUTO or the context's plan).
+ * Creutz demons, if any, are dropped. Asynchronous on the context's stream.
+ * Errors: EINVAL (invalid params, another side or plan), ESTATE (poisoned),
+ * EDEVICE. */
+int ising_reset(ising_ctx* ctx, const ising_params* params);
+
+/* Make room now for the per-sweep series of `sweeps` further sweeps, so that
+ * later ising_sweep and batch calls covering them allocate nothing (growing
+ * the series buffer synchronises the context's stream). Errors: EINVAL,
+ * ESTATE, ERANGE (the sweep index would pass 2^32), ENOMEM. */
+int ising_reserve(ising_ctx* ctx, uint64_t sweeps);
+
 /* Release the context and its library-owned device memory. NULL is a no-op.
  * Synchronises the context's stream first. */
 int ising_destroy(ising_ctx* ctx);

@@ -79,6 +79,8 @@ class IsingError(RuntimeError):
 SIGNATURES = {
     "ising_state_bytes": (C.c_size_t, [C.c_uint32, C.c_uint32]),
     "ising_create": (C.c_int, [C.POINTER(ising_params), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "ising_reset": (C.c_int, [C.c_void_p, C.POINTER(ising_params)]),
+    "ising_reserve": (C.c_int, [C.c_void_p, C.c_uint64]),
     "ising_create_in": (C.c_int, [C.POINTER(ising_params), C.c_void_p, C.c_size_t, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "ising_sweep": (C.c_int, [C.c_void_p, C.c_uint64]),
@@ -172,6 +174,17 @@ def ising_create(L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN
     out = C.c_void_p()
     _check(lib().ising_create(C.byref(p), stream, C.byref(out)), "ising_create")
     return out.value
+
+
+def ising_reset(ctx, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO):
+    """Re-initialise ctx for new parameters of the same side, keeping its buffers."""
+    p = _params(L, J, h, T, seed, p_up, flags)
+    _check(lib().ising_reset(ctx, C.byref(p)), "ising_reset", ctx)
+
+
+def ising_reserve(ctx, sweeps):
+    """Make room for the series of `sweeps` further sweeps."""
+    _check(lib().ising_reserve(ctx, int(sweeps)), "ising_reserve", ctx)
 
 
 def ising_create_in(dev_ptr, nbytes, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0.5, flags=ISING_PLAN_AUTO,

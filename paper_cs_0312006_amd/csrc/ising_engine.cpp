@@ -63,6 +63,7 @@ struct Engine {
     // stepped plan, fused walk (sides multiple of 16)
     hipGraph_t fgraph = nullptr;
     hipGraphExec_t fexec = nullptr;
+    uint32_t fslots = 0;  // waves of the fused walk resident on the GPU at once
 };
 
 constexpr uint32_t kSweepsPerReplay = 16;
@@ -159,6 +160,7 @@ hipError_t init_engine(Engine& e) {
     if (per_cu < 1) per_cu = 1;
     e.grid = (uint32_t)prop.multiProcessorCount * (uint32_t)per_cu;
     e.mgrid = (uint32_t)prop.multiProcessorCount * 8u;
+    e.fslots = multi_fused_wave_slots((uint32_t)prop.multiProcessorCount);
     e.ready = true;
     return hipSuccess;
 }
@@ -302,17 +304,29 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         e.h_hdr->count = live;
         e.h_hdr->head = 0;
     } else {
+        // fused walk: the tallest tiles (32 rows) that still give every wave
+        // slot of the GPU about two tiles; fewer rows for a few large lattices
+        uint32_t rows = 32u;
+        if (fused) {
+            const uint64_t want = 2ull * e.fslots;
+            for (; rows > 8u; rows /= 2u) {
+                uint64_t tiles = 0;
+                for (size_t k = 0; k < count; ++k)
+                    if (n[k]) tiles += multi_fused_tiles(e.h_items[k].L, rows);
+                if (tiles >= want) break;
+            }
+        }
         uint64_t vb = 0;
         for (size_t k = 0; k < count; ++k) {
             e.h_vbs[k] = (uint32_t)vb;
-            vb += fused ? multi_fused_tiles(e.h_items[k].L) : multi_vblocks(e.h_items[k].L, e.h_items[k].cw);
+            vb += fused ? multi_fused_tiles(e.h_items[k].L, rows) : multi_vblocks(e.h_items[k].L, e.h_items[k].cw);
         }
         if (vb >= ((uint64_t)1 << 32)) return ISING_ERANGE;
         e.h_vbs[count] = (uint32_t)vb;
         e.h_mhdr->n_items = (uint32_t)count;
         e.h_mhdr->total_vblocks = (uint32_t)vb;
         e.h_mhdr->s_base = 0u - kSweepsPerReplay;  // the graph's first node adds G
-        e.h_mhdr->pad = 0;
+        e.h_mhdr->rows = rows;
     }
 
     // order the launch after every context's earlier work

@@ -5,9 +5,10 @@
 //
 // Each lattice ping-pongs between its two buffers: sweep s of a call reads
 // buffer s & 1 of the item (p = the current lattice, q = the other one) and
-// writes the other. A wave walks one tile of up to 32 rows by 128 words of
-// a plane row (two words per lane), exactly as the single-lattice fused
-// kernel does, with two differences:
+// writes the other. A wave walks one tile of up to 32 rows (8 or 16 when a
+// call has too few tiles to fill the GPU) by 128 words of a plane row (two
+// words per lane), exactly as the single-lattice fused kernel does, with two
+// differences:
 //   - tiles at a lattice's right and bottom edges may be narrower and
 //     shorter: lanes past the lattice's last word shadow its last lane
 //     (their loads stay in range, nothing of theirs is stored or counted),
@@ -38,7 +39,7 @@ __device__ __forceinline__ uint32_t wrap_row_m(int i, uint32_t L) {
 // Partial (B, M) of one tile of item `it` for its sweep `s` of this call.
 template <bool EXACT>
 __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it, uint32_t tx, uint32_t ty,
-                                        uint32_t s, int64_t& b_out, int64_t& m_out) {
+                                        uint32_t rows, uint32_t s, int64_t& b_out, int64_t& m_out) {
     constexpr int CW = kMfCW;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t L = it.L, Hw = it.Hw, k0 = it.k0, k1 = it.k1;
@@ -49,8 +50,8 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
     const bool active = lane <= la;
     const bool is_last = lane == la;
     const uint32_t x = X0 + min(lane, la) * CW;
-    const int r0 = (int)(ty * kMultiFusedRows);
-    const int R = (int)min(kMultiFusedRows, L - ty * kMultiFusedRows);  // 16 or 32 rows (L % 16 == 0)
+    const int r0 = (int)(ty * rows);
+    const int R = (int)min(rows, L - ty * rows);  // a multiple of 8 (L % 16 == 0, rows in {8, 16, 32})
     const uint32_t xl = X0 == 0 ? Hw - 1 : X0 - 1;
     const uint32_t xr = X0 + wds == Hw ? 0u : X0 + wds;
     const bool odd = (s & 1u) != 0u;
@@ -177,6 +178,7 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
     const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t n_items = hdr->n_items, total = hdr->total_vblocks;
     const uint32_t sweep = hdr->s_base + s;
+    const uint32_t rows = hdr->rows;
     const uint32_t waves = gridDim.x * (kMfThreads / 64);
     for (uint32_t g0 = blockIdx.x * (kMfThreads / 64) + wv; g0 < total; g0 += waves) {
         const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
@@ -198,8 +200,8 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
         const uint32_t tile = g - tile_start[lo];
         const uint32_t tx = tile % n_tx, ty = tile / n_tx;
         int64_t b, m;
-        if (it.exact) mf_tile<true>(lt[wv], it, tx, ty, sweep, b, m);
-        else mf_tile<false>(lt[wv], it, tx, ty, sweep, b, m);
+        if (it.exact) mf_tile<true>(lt[wv], it, tx, ty, rows, sweep, b, m);
+        else mf_tile<false>(lt[wv], it, tx, ty, rows, sweep, b, m);
         if (lane == 0) {
             atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep]), (unsigned long long)b);
             atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep + 1]), (unsigned long long)m);
@@ -219,9 +221,19 @@ __global__ void __launch_bounds__(256) k_multi_fused_clear(const BatchItem* __re
 
 bool multi_fused_supported(uint32_t L) { return L % 16u == 0u && L >= 16u; }
 
-uint32_t multi_fused_tiles(uint32_t L) {
+uint32_t multi_fused_tiles(uint32_t L, uint32_t rows) {
     const uint32_t Hw = L / 8u;
-    return ((Hw + kMfTileWords - 1) / kMfTileWords) * ((L + kMultiFusedRows - 1) / kMultiFusedRows);
+    return ((Hw + kMfTileWords - 1) / kMfTileWords) * ((L + rows - 1) / rows);
+}
+
+uint32_t multi_fused_wave_slots(uint32_t cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_multi_fused, (int)kMfThreads, 0) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    return cus * (uint32_t)per_cu * (kMfThreads / 64);
 }
 
 hipError_t launch_multi_fused_clear(const BatchItem* items, uint32_t n_items, hipStream_t s) {

@@ -401,6 +401,40 @@ int ising_create_in(const ising_params* params, void* dev_buf, size_t bytes, voi
     return create_common(params, dev_buf, bytes, stream, out);
 }
 
+int ising_reset(ising_ctx* ctx, const ising_params* params) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (!valid_params(params) || params->L != ctx->L) return ISING_EINVAL;
+    const uint32_t kind = params->flags & 0xffu;
+    if (kind != ISING_PLAN_AUTO && kind != ctx->plan.kind) return ISING_EINVAL;
+    if (ctx->demon || ctx->demon_alt) {
+        // earlier work on the context's stream may still read the demons
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->demon) (void)hipFree(ctx->demon);
+        if (ctx->demon_alt) (void)hipFree(ctx->demon_alt);
+        ctx->demon = nullptr;
+        ctx->demon_alt = nullptr;
+    }
+    // the new initial lattice is drawn on the context's stream, after all of
+    // its earlier work
+    ctx->p = *params;
+    build_accept_table(params->J, params->h, params->T, &ctx->table, &ctx->exact);
+    ctx->cur = 0;
+    ctx->t = 0;
+    ctx->series_len = 0;
+    const uint64_t pthr = (uint64_t)std::floor(params->p_up * 4294967296.0);
+    HIP_TRY(ctx, launch_init(ctx_planes(ctx), (ctx->L % 8u) == 0u, (uint32_t)params->seed,
+                             (uint32_t)(params->seed >> 32), pthr, ctx->stream));
+    return ISING_OK;
+}
+
+int ising_reserve(ising_ctx* ctx, uint64_t sweeps) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (ctx->t + sweeps > ((uint64_t)1 << 32)) return ISING_ERANGE;
+    return ctx_reserve_series(ctx, sweeps);
+}
+
 int ising_sweep(ising_ctx* ctx, uint64_t n) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;

@@ -6,7 +6,9 @@ final bond sum and magnetisation and FP64 averages of the per-sweep series.
 
 The loop works in epochs. Every request admitted so far advances by up to
 `epoch_sweeps` sweeps in one batched call (`ising_sweep_batch_plan`, the
-stepped plan, which spreads every lattice over the whole GPU). Between
+stepped plan, which spreads every lattice over the whole GPU; with sides
+that are multiples of 16 each sweep is one pass over the tiles of all
+lattices, every lattice alternating between two buffers). Between
 epochs, requests that have arrived are admitted first come, first served,
 as long as the HBM budget (the sum of the admitted lattices' device bytes)
 and the slot limit allow; requests whose sweeps are done are retired.
@@ -47,19 +49,39 @@ class Result:
 
 
 class GpuExecutor:
-    """Executor over the C ABI (one stream per request)."""
+    """Executor over the C ABI (one stream per request).
 
-    def __init__(self, hash_results=True):
+    Retired contexts are kept, up to `pool_per_side` of each side, and
+    re-initialised for later requests of that side (ising_reset) instead of
+    being freed and allocated again: freeing device memory synchronises the
+    device, which would drain the epochs queued behind it. A new request's
+    whole series is reserved at admission, so no epoch grows it. close()
+    releases the kept contexts."""
+
+    def __init__(self, hash_results=True, pool_per_side=8):
         from . import binding as b
         self.b = b
         b.lib()
         self.hash_results = hash_results
+        self.pool_per_side = pool_per_side
+        self.pool = collections.defaultdict(list)  # side -> idle contexts
+        self.side = {}                             # context -> side
 
     def bytes_for(self, run):
-        return self.b.ising_state_bytes(run.L, self.b.ISING_PLAN_TWO_PASS) or run.L * run.L
+        # the stepped plan alternates a lattice between two buffers
+        return self.b.ising_state_bytes(run.L, self.b.ISING_PLAN_FUSED) or 2 * run.L * run.L
 
     def create(self, run):
-        return self.b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, self.b.ISING_PLAN_TWO_PASS)
+        b = self.b
+        idle = self.pool.get(run.L)
+        if idle:
+            handle = idle.pop()
+            b.ising_reset(handle, run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
+        else:
+            handle = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
+            self.side[handle] = run.L
+        b.ising_reserve(handle, run.sweeps)
+        return handle
 
     def step(self, handles, sweeps):
         self.b.ising_sweep_batch_plan(handles, sweeps, self.b.ISING_BATCH_STEPPED)
@@ -74,7 +96,19 @@ class GpuExecutor:
                 "e_mean": avg.e, "abs_m_mean": avg.abs_m}
 
     def destroy(self, handle):
-        self.b.ising_destroy(handle)
+        L = self.side[handle]
+        if len(self.pool[L]) < self.pool_per_side:
+            self.pool[L].append(handle)
+        else:
+            del self.side[handle]
+            self.b.ising_destroy(handle)
+
+    def close(self):
+        for handles in self.pool.values():
+            for handle in handles:
+                self.b.ising_destroy(handle)
+                del self.side[handle]
+        self.pool.clear()
 
 
 def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=64,

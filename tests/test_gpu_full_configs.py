@@ -66,7 +66,11 @@ def test_served_full_size_requests_equal_solo(b, o):
     t0 = min(reqs[k].arrival for k in chosen)
     sub = [W.Request(reqs[k].arrival - t0, reqs[k].run) for k in chosen]
     G.log("served 12 full-size requests")
-    res, stats = serve.serve(sub, serve.GpuExecutor(), epoch_sweeps=64)
+    ex = serve.GpuExecutor()
+    try:
+        res, stats = serve.serve(sub, ex, epoch_sweeps=64)
+    finally:
+        ex.close()
     assert all(not r.error for r in res)
     for r in res:
         run = sub[r.rid].run

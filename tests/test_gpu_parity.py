@@ -133,6 +133,39 @@ def test_load_spins_rejects_bad_bytes(b):
     b.ising_destroy(ctx)
 
 
+def test_reset_equals_create_and_rejects_other_sides(b, o):
+    """ising_reset re-initialises a used context (sweeps done, Creutz demons
+    set) for new parameters of the same side: the run that follows equals
+    the oracle's run of those parameters; demons are gone; another side or
+    plan is rejected; ising_reserve rejects sweeps past the index limit."""
+    ctx = b.ising_create(64, 1.0, 0.0, 1.5, 3, 1.0, b.ISING_PLAN_TWO_PASS)
+    try:
+        b.ising_sweep(ctx, 7)
+        b.ising_creutz_init(ctx, None, 2)
+        run = W.Run(L=64, J=-1.0, h=0.0, T=2.5, seed=9, p_up=0.5, sweeps=13)
+        b.ising_reset(ctx, run.L, run.J, run.h, run.T, run.seed, run.p_up)
+        b.ising_reserve(ctx, run.sweeps)
+        b.ising_sweep(ctx, run.sweeps)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        assert obs.sweeps_done == run.sweeps and len(B) == run.sweeps
+        G.assert_same({"spins": b.ising_copy_spins(ctx, 64), "B": B, "M": M, "hash": obs.lattice_hash},
+                      G.oracle_run(o, run), "reset")
+        with pytest.raises(b.IsingError) as e:
+            b.ising_demon_sum(ctx)
+        assert e.value.code == b.ISING_ESTATE
+        with pytest.raises(b.IsingError) as e:
+            b.ising_reset(ctx, 32)
+        assert e.value.code == b.ISING_EINVAL
+        with pytest.raises(b.IsingError) as e:
+            b.ising_reset(ctx, 64, flags=b.ISING_PLAN_GENERIC)
+        assert e.value.code == b.ISING_EINVAL
+        with pytest.raises(b.IsingError) as e:
+            b.ising_reserve(ctx, 1 << 33)
+        assert e.value.code == b.ISING_ERANGE
+    finally:
+        b.ising_destroy(ctx)
+
+
 def test_sweep_index_limit(b):
     ctx = b.ising_create(16)
     b.ising_load_spins(ctx, np.ones((16, 16), dtype=np.int8), 2 ** 32 - 2)

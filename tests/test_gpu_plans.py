@@ -179,6 +179,30 @@ def test_batch_stepped_fused_walk_ragged_tiles(b, o):
                       G.oracle_run(o, r, sweeps=r.sweeps + e), f"stepped fused L={r.L}")
 
 
+def test_batch_stepped_fused_walk_many_large_lattices(b):
+    """A stepped batch of 48 lattices of 2048^2 (h = 0 and h = 0.05): tiles
+    of fewer rows are used when the batch has too few tiles to fill the GPU
+    (this batch sits between the 8-lattice test above and the 1024-lattice
+    configuration, which use the shortest and the tallest tiles). Every
+    lattice's series and final lattice equal its own run alone (two-pass
+    plan), over an odd and then an even number of sweeps."""
+    runs = [W.Run(L=2048, J=1.0, h=0.05 * (k % 2), T=2.0 + 0.02 * k, seed=100 + k, p_up=0.5, sweeps=3)
+            for k in range(48)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    G.log("stepped fused walk: 48 x 2048^2")
+    b.ising_sweep_batch_plan(ctxs, [3] * 48, b.ISING_BATCH_STEPPED)
+    b.ising_sweep_batch_plan(ctxs, [2] * 48, b.ISING_BATCH_STEPPED)
+    for k, (r, ctx) in enumerate(zip(runs, ctxs)):
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        b.ising_destroy(ctx)
+        if k % 6:
+            continue
+        G.log(f"stepped fused walk: 2048^2 lattice {k} vs its solo run")
+        ref = G.gpu_run(b, r, sweeps=5, plan=b.ISING_PLAN_TWO_PASS)
+        assert obs.lattice_hash == ref["hash"]
+        assert np.array_equal(B, ref["B"]) and np.array_equal(M, ref["M"])
+
+
 def test_batch_rejects_before_launching(b):
     good = b.ising_create(16)
     bad = b.ising_create(10)  # L % 8 != 0

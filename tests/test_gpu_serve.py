@@ -35,7 +35,11 @@ def _solo(b, run):
 def test_served_results_equal_solo_results(b, budget, epoch):
     reqs = W.request_stream(2000.0, count=24, rng_seed=11, sweeps_range=(40, 300), side_units=(1, 8))
     G.log(f"serve 24 requests budget={budget} epoch={epoch}")
-    res, stats = serve.serve(reqs, serve.GpuExecutor(), hbm_budget=budget, epoch_sweeps=epoch)
+    ex = serve.GpuExecutor()
+    try:
+        res, stats = serve.serve(reqs, ex, hbm_budget=budget, epoch_sweeps=epoch)
+    finally:
+        ex.close()
     assert len(res) == 24 and all(not r.error for r in res)
     assert stats["epochs"] > 1
     for r in res:
@@ -53,7 +57,11 @@ def test_served_small_requests_match_oracle(b):
     o.set_threads(G.host_threads())
     reqs = W.request_stream(5000.0, count=8, rng_seed=4, sweeps_range=(20, 60), side_units=(1, 2))
     G.log("serve 8 small requests vs oracle")
-    res, _ = serve.serve(reqs, serve.GpuExecutor(), epoch_sweeps=9)
+    ex = serve.GpuExecutor()
+    try:
+        res, _ = serve.serve(reqs, ex, epoch_sweeps=9)
+    finally:
+        ex.close()
     for r in res:
         run = reqs[r.rid].run
         s = o.init(run.L, run.seed, run.p_up)
