@@ -29,7 +29,7 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit op
 # sources (profiles/k_fused_ising2d_32768.md), per tile shape. They are
 # reported only while the kernel sources hash to the recorded value and the
 # timed plan is one of these; otherwise they are null.
-PROFILED_SOURCES = "4298ffdfeae5e772"
+PROFILED_SOURCES = "c43d723904657924"
 PROFILED = {
     # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch, mean of 54)
     "k_fused<4,32>": {"hbm_bytes_per_launch": (690127.8 * 2.0 + 1048863.4) * 1024,
@@ -44,7 +44,7 @@ PROFILED = {
 
 # Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md),
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch, mean of 22
-PROFILED_CREUTZ_SOURCES = "5d841d88b00425db"
+PROFILED_CREUTZ_SOURCES = "f4a1580765787689"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
                    "hbm_bytes_per_sweep": (1316828.2 * 2.0 + 2097585.8) * 1024}
 
