@@ -373,8 +373,9 @@ static int create_common(const ising_params* params, void* dev_buf, size_t bytes
         ising_destroy(ctx);
         return ISING_ENOMEM;
     }
+    // the series buffer is allocated by the first sweep or ising_reserve, so
+    // that a caller reserving its whole run allocates it once, with no free
     int rc = ctx_prepare_plan(ctx);
-    if (rc == ISING_OK) rc = ctx_reserve_series(ctx, 1024);
     if (rc != ISING_OK) {
         ising_destroy(ctx);
         return rc;
@@ -530,6 +531,33 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t) {
     return ISING_OK;
 }
 
+// Pinned host memory of at least `bytes`, kept by the context for reading
+// observables back. A device-to-host copy into pinned memory goes to a DMA
+// engine and is ordered by its stream alone; a copy into pageable memory is
+// staged by the runtime through copy kernels on the stream's hardware queue,
+// where it can wait behind other streams' kernels that share the queue.
+// Returns nullptr when `bytes` exceeds kMaxHostStage or the allocation fails:
+// the caller then reads into pageable memory. The stage only grows, and only
+// between calls (each read-back is synchronised before it returns).
+static constexpr size_t kMaxHostStage = (size_t)64 << 20;
+
+static void* ctx_host_stage(ising_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->host_stage_bytes) return ctx->host_stage;
+    if (bytes > kMaxHostStage) return nullptr;
+    const size_t series_bytes = (size_t)ctx->series_cap * 2 * sizeof(int64_t);
+    size_t want = std::max<size_t>(bytes, std::min(kMaxHostStage, series_bytes));
+    want = std::max<size_t>(want, 4096);
+    void* fresh = nullptr;
+    if (hipHostMalloc(&fresh, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    ctx->host_stage = fresh;
+    ctx->host_stage_bytes = want;
+    return fresh;
+}
+
 int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int64_t* mag_series,
                       uint64_t capacity, uint32_t want) {
     int rc = ctx_enter(ctx);
@@ -537,46 +565,47 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
     if (want & ~(ISING_OBS_HASH | ISING_OBS_SERIES)) return ISING_EINVAL;
     const uint64_t len = ctx->series_len;
     if ((want & ISING_OBS_SERIES) && (bond_series || mag_series) && capacity < len) return ISING_ERANGE;
-    int64_t bm[2] = {0, 0};
-    std::vector<int64_t> ser;
+    const size_t N = (size_t)ctx->L * ctx->L;
     const bool copy_series = (want & ISING_OBS_SERIES) && len && (bond_series || mag_series);
-    if (copy_series) {
+    const bool hash = (want & ISING_OBS_HASH) != 0;
+    const size_t ser_bytes = (copy_series ? 2 * len : 2) * sizeof(int64_t);
+    const size_t hash_off = (ser_bytes + 255) & ~(size_t)255;
+    // read back into the context's pinned stage when it fits, else into
+    // pageable memory
+    uint8_t* stage = static_cast<uint8_t*>(ctx_host_stage(ctx, hash ? hash_off + N : ser_bytes));
+    std::vector<int64_t> ser_pageable;
+    std::vector<uint8_t> bytes_pageable;
+    if (!stage) {
         try {
-            ser.resize(2 * len);
+            ser_pageable.resize(ser_bytes / sizeof(int64_t));
+            if (hash) bytes_pageable.resize(N);
         } catch (...) {
             return ISING_ENOMEM;
         }
-        HIP_TRY(ctx, hipMemcpyAsync(ser.data(), ctx->series, 2 * len * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                    ctx->stream));
+    }
+    int64_t* ser = stage ? reinterpret_cast<int64_t*>(stage) : ser_pageable.data();
+    uint8_t* bytes = stage ? stage + hash_off : bytes_pageable.data();
+    if (copy_series) {
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series, ser_bytes, hipMemcpyDeviceToHost, ctx->stream));
     } else if (len) {
         // the last series entry is the current lattice's (B, M)
-        HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->series + 2 * (len - 1), sizeof(bm), hipMemcpyDeviceToHost,
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series + 2 * (len - 1), ser_bytes, hipMemcpyDeviceToHost,
                                     ctx->stream));
     } else {
         HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
-        HIP_TRY(ctx, hipMemcpyAsync(bm, ctx->scratch, sizeof(bm), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->scratch, ser_bytes, hipMemcpyDeviceToHost, ctx->stream));
     }
-    uint64_t hsh = 0;
-    if (want & ISING_OBS_HASH) {
-        const size_t N = (size_t)ctx->L * ctx->L;
+    if (hash) {
         rc = ensure_canonical(ctx);
         if (rc != ISING_OK) return rc;
-        std::vector<uint8_t> bytes;
-        try {
-            bytes.resize(N);
-        } catch (...) {
-            return ISING_ENOMEM;
-        }
         HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
-        HIP_TRY(ctx, hipMemcpyAsync(bytes.data(), ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-        hsh = fnv1a64(bytes.data(), N);
-    } else {
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(bytes, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
     }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const uint64_t hsh = hash ? fnv1a64(bytes, N) : 0;
+    const int64_t* last = copy_series ? ser + 2 * (len - 1) : ser;
+    const int64_t bm[2] = {last[0], last[1]};
     if (copy_series) {
-        bm[0] = ser[2 * (len - 1)];
-        bm[1] = ser[2 * (len - 1) + 1];
         for (uint64_t k = 0; k < len; ++k) {
             if (bond_series) bond_series[k] = ser[2 * k];
             if (mag_series) mag_series[k] = ser[2 * k + 1];
@@ -913,6 +942,7 @@ int ising_destroy(ising_ctx* ctx) {
         if (ctx->cfpart[k]) (void)hipFree(ctx->cfpart[k]);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->canon) (void)hipFree(ctx->canon);
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipGetLastError();
     delete ctx;

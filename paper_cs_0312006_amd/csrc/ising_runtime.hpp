@@ -45,6 +45,8 @@ struct ising_ctx {
     uint32_t part_cap = 0;       // pairs per partial buffer
     int64_t* scratch = nullptr;  // 4 int64 for observables
     int8_t* canon = nullptr;     // N bytes, canonical layout staging
+    void* host_stage = nullptr;  // pinned host memory the observables are read back into
+    size_t host_stage_bytes = 0;
     uint8_t* demon = nullptr;    // Creutz demons (N bytes, colour-plane layout), once initialised
     uint8_t* demon_alt = nullptr;  // second demon buffer for the fused (ping-pong) Creutz sweep
     int64_t* cpart = nullptr;    // Creutz per-block (B, M) partials

@@ -17,10 +17,10 @@ Because the draws are keyed by (seed, sweep, colour, site), a request's
 result does not depend on which epochs or which other requests it shared
 the GPU with.
 
-The next epoch is enqueued before the current one is waited for: which
-requests take part and how many sweeps each runs is known in advance, and
-every request has its own stream, so retiring a request waits only for
-the epochs it was part of.
+Up to `depth` epochs are enqueued before the oldest one is waited for:
+which requests take part and how many sweeps each runs is known in
+advance, and every request has its own stream, so retiring a request
+waits only for the epochs it was part of.
 """
 import collections
 import math
@@ -54,16 +54,18 @@ class GpuExecutor:
     Retired contexts are kept, up to `pool_per_side` of each side, and
     re-initialised for later requests of that side (ising_reset) instead of
     being freed and allocated again: freeing device memory synchronises the
-    device, which would drain the epochs queued behind it. A new request's
-    whole series is reserved at admission, so no epoch grows it. close()
+    device, which would drain the epochs queued behind it. Every context's
+    series is reserved at admission for at least `series_floor` sweeps (and
+    the whole request), so neither an epoch nor a reuse grows it. close()
     releases the kept contexts."""
 
-    def __init__(self, hash_results=True, pool_per_side=8):
+    def __init__(self, hash_results=True, pool_per_side=8, series_floor=32768):
         from . import binding as b
         self.b = b
         b.lib()
         self.hash_results = hash_results
         self.pool_per_side = pool_per_side
+        self.series_floor = series_floor  # every context's series holds at least this many sweeps
         self.pool = collections.defaultdict(list)  # side -> idle contexts
         self.side = {}                             # context -> side
 
@@ -80,7 +82,7 @@ class GpuExecutor:
         else:
             handle = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
             self.side[handle] = run.L
-        b.ising_reserve(handle, run.sweeps)
+        b.ising_reserve(handle, max(run.sweeps, self.series_floor))
         return handle
 
     def step(self, handles, sweeps):
@@ -112,9 +114,11 @@ class GpuExecutor:
 
 
 def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=64,
-          clock=time.perf_counter, sleep=time.sleep):
+          clock=time.perf_counter, sleep=time.sleep, depth=2):
     """Run a stream of workloads.Request through the executor. Returns
-    (results sorted by request id, stats)."""
+    (results sorted by request id, stats). Up to `depth` epochs are enqueued
+    ahead of the one being retired, so that the host's admission and
+    retirement work overlaps the GPU's sweeps."""
     order = sorted(range(len(requests)), key=lambda k: requests[k].arrival)
     future = collections.deque(order)          # not yet arrived
     waiting = collections.deque()              # arrived, not admitted
@@ -123,7 +127,7 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=6
     results = {}
     epochs = 0
     t0 = clock()
-    in_flight = None                           # (ids, sweeps) of the enqueued epoch not yet retired
+    in_flight = collections.deque()            # (ids, sweeps) of enqueued epochs not yet retired, oldest first
 
     def now():
         return clock() - t0
@@ -164,24 +168,26 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=6
 
     while future or waiting or active or in_flight:
         admit()
-        # the next epoch: every active request not already finishing in the
-        # epoch in flight advances by up to epoch_sweeps
-        pending = {}
-        if in_flight:
-            for rid, n in zip(*in_flight):
-                pending[rid] = n
+        # the next epoch: every active request with sweeps left after the
+        # epochs in flight advances by up to epoch_sweeps
+        pending = collections.Counter()
+        for e_ids, e_sweeps in in_flight:
+            for rid, n in zip(e_ids, e_sweeps):
+                pending[rid] += n
         ids, sweeps = [], []
         for rid, slot in active.items():
-            left = slot[1] - pending.get(rid, 0)
+            left = slot[1] - pending[rid]
             if left > 0:
                 ids.append(rid)
                 sweeps.append(min(epoch_sweeps, left))
         if ids:
             executor.step([active[r][0] for r in ids], sweeps)
             epochs += 1
-        if in_flight:
-            retire(*in_flight)
-        in_flight = (ids, sweeps) if ids else None
+            in_flight.append((ids, sweeps))
+        # retire the oldest epoch once `depth` are queued behind it, or when
+        # nothing new could be enqueued
+        if in_flight and (len(in_flight) > depth or not ids):
+            retire(*in_flight.popleft())
         if not in_flight and not active and future and not waiting:
             sleep(max(0.0, requests[future[0]].arrival - now()))
     makespan = now()
