@@ -48,6 +48,47 @@ PROFILED_CREUTZ_SOURCES = "f4a1580765787689"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
                    "hbm_bytes_per_sweep": (1316828.2 * 2.0 + 2097585.8) * 1024}
 
+# Batched configuration (1024 lattices, 10000 sweeps): the bit-packed
+# resident kernel the AUTO plan runs (profiles/k_batch_bits_batched_1024.md,
+# one dispatch of 2000 sweeps) and the stepped plan's fused walk
+# (profiles/k_multi_fused_batched_1024.md, mean per dispatch; FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0 KiB)
+BATCH_FILES = ("ising_batch.hip", "ising_device.hpp", "ising_launch.hpp")
+PROFILED_BATCH_SOURCES = "f19eaf059be312b5"
+PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
+                  "valu_lane_ops_per_attempt": 193586363985.0 * 64 / (388630784 * 2000),
+                  "valu_busy_rocprof": 0.957}
+MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
+PROFILED_MULTI_FUSED_SOURCES = "4dbb36eea9d9c09f"
+PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
+                        "valu_lane_ops_per_attempt": 138164578.0 * 64 / 388630784,
+                        "valu_busy_rocprof": 0.779,
+                        # share of the tiles' lane slots that hold lattice words
+                        # in this configuration (sum L^2 / sum 1024 L)
+                        "lanes_on_lattice_words": 0.683,
+                        "hbm_bytes_per_sweep": (264871.1 * 2.0 + 382840.4) * 1024}
+
+
+def batched_roofline(res, stepped):
+    """ALU roof of the batched leg's kernel from its profiled ops per site
+    update, or None when its sources have changed since the profile."""
+    files, src, prof = ((MULTI_FUSED_FILES, PROFILED_MULTI_FUSED_SOURCES, PROFILED_MULTI_FUSED) if stepped
+                        else (BATCH_FILES, PROFILED_BATCH_SOURCES, PROFILED_BATCH))
+    if kernel_sources_hash(files) != src:
+        return None
+    ops = prof["valu_lane_ops_per_attempt"] * res["value"] * 1e9
+    roof = {"bound": "alu", "achieved": ops / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+            "unit": "T lane-ops/s (32-bit VALU)", "frac": ops / VALU_PEAK_LANE_OPS, "kernel": prof["kernel"],
+            "ops_per_attempt": prof["valu_lane_ops_per_attempt"], "valu_busy_rocprof": prof["valu_busy_rocprof"],
+            "traffic": None}
+    if stepped:
+        sweep_s = res["ms"] * 1e-3 / res["sweeps"]
+        roof["traffic"] = prof["hbm_bytes_per_sweep"] / sweep_s / 1e9
+        roof["traffic_unit"] = "GB/s"
+        roof["algorithmic_hbm_GBs"] = 2.0 * res["attempts"] / res["sweeps"] / sweep_s / 1e9
+        roof["lanes_on_lattice_words"] = prof["lanes_on_lattice_words"]
+    return roof
+
 
 def kernel_sources_hash(files=("ising_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")):
     import hashlib
@@ -490,7 +531,8 @@ def main():
     ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--epoch-sweeps", type=int, default=64)
     ap.add_argument("--creutz-sweeps", type=int, default=100)
-    ap.add_argument("--only", choices=["creutz", "percolation", "percolation-media", "micro"], default=None,
+    ap.add_argument("--only", default=None,
+                    choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped"],
                     help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
@@ -514,6 +556,9 @@ def main():
             leg = run_percolation(b, cpu=False)
         elif args.only == "percolation-media":
             leg = run_percolation(b, cpu=False, spanning=False)
+        elif args.only in ("batched", "batched-stepped"):
+            leg, _ = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0,
+                                 plan=0 if args.only == "batched" else 2)
         else:
             leg = run_micro(b, torch, stream)
         print(json.dumps({"leg": args.only, "result": leg}), flush=True)
@@ -589,9 +634,11 @@ def main():
         # configuration (h = 0, L <= 1024) held bit-packed in workgroup memory
         auto, h_au = run_batched(b, torch, stream, 1024, args.batched_sweeps, args.batched_sample, plan=0)
         auto["plan"] = "auto: resident, lattices bit-packed in workgroup memory"
+        auto["roofline"] = batched_roofline(auto, stepped=False)
         stepped, h_st = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=2)
         auto["stepped_plan_same_config"] = {"value": stepped["value"], "ms": stepped["ms"],
-                                            "results_identical": h_st == h_au}
+                                            "results_identical": h_st == h_au,
+                                            "roofline": batched_roofline(stepped, stepped=True)}
         out["batched"] = auto
 
     if not args.no_extra and not args.no_served:
