@@ -175,8 +175,10 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
  * ISING_BATCH_RESIDENT: one persistent launch, each workgroup runs whole
  *   lattices (every sweep) taken from a work queue, largest first. A lattice
  *   with h = 0 and side up to 1072 is held in the workgroup's local memory
- *   at one bit per site for all its sweeps; other lattices of side up to 256
- *   are held there as bytes; larger ones are swept in global memory;
+ *   at one bit per site for all its sweeps, except that while the batch has
+ *   fewer lattices than the launch has workgroups, those of side up to 256
+ *   are held as bytes (lower latency per sweep); other lattices of side up
+ *   to 256 are held there as bytes; larger ones are swept in global memory;
  * ISING_BATCH_STEPPED: every sweep is one launch over the tiles of all
  *   lattices, so each lattice is spread over the whole GPU; sweeps are
  *   replayed from a captured graph in groups of 16. When every side is a

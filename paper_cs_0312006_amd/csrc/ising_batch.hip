@@ -424,6 +424,11 @@ bool bits_fit(uint32_t L) {
     return 2ull * L * wr * 4ull <= kBatchBitsLdsBytes;
 }
 
+bool bytes_fit(uint32_t L) {
+    const uint64_t plane_words = (uint64_t)L * (L / 8u);
+    return 2ull * plane_words * 4ull <= kBatchLdsBytes;
+}
+
 uint32_t batch_block_threads() { return kBatchThreads; }
 
 hipError_t batch_occupancy(int* blocks_per_cu) {

@@ -261,6 +261,13 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     }
     std::vector<uint64_t> work(count);
     uint32_t live = 0;
+    for (size_t k = 0; k < count; ++k)
+        if (n[k]) ++live;
+    // A thread updates a bit-packed word with eight Philox blocks where a
+    // byte word takes one, so bits trade a lattice's latency for local
+    // memory. While the batch leaves workgroups idle, latency decides: a
+    // lattice that fits in local memory as bytes stays bytes.
+    const bool saturated = live >= e.grid;
     for (size_t k = 0; k < count; ++k) {
         ising_ctx* c = ctxs[k];
         const Planes pl = ctx_planes(c);
@@ -286,11 +293,10 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         it.k0 = (uint32_t)c->p.seed;
         it.k1 = (uint32_t)(c->p.seed >> 32);
         it.exact = c->exact ? 1u : 0u;
-        it.bits = (!stepped && bits_fit(c->L)) ? bits_mode(c->table) : 0u;
+        it.bits = (!stepped && bits_fit(c->L) && (saturated || !bytes_fit(c->L))) ? bits_mode(c->table) : 0u;
         it.pad = 0;
         it.table = c->table;
         work[k] = (uint64_t)c->L * c->L * n[k];
-        if (n[k]) ++live;
     }
     uint64_t max_n = 0;
     for (size_t k = 0; k < count; ++k) max_n = std::max<uint64_t>(max_n, n[k]);

@@ -122,6 +122,8 @@ constexpr uint32_t kBatchBitsLdsBytes = 147456;
 uint32_t bits_mode(const AcceptTable& at);
 // Whether an L x L lattice fits the bit-packed LDS area.
 bool bits_fit(uint32_t L);
+// Whether a side-L lattice fits the resident kernel's local memory as bytes.
+bool bytes_fit(uint32_t L);
 
 hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,
                         hipStream_t s);

@@ -121,12 +121,12 @@ def test_batch_equals_solo_and_oracle(b, o, plan):
 
 
 def test_batch_bit_packed_couplings_and_sides(b, o):
-    """The resident batch's bit-packed path (h = 0, side up to 1072): J > 0,
-    J < 0 and J = 0, thresholds of 0 (T = 0.05), near 1 (T = 50) and at T_c,
-    sides with partial 32-site words (8, 24, 40, 136), the largest sides that
-    fit local memory (1072, 1080) and one that does not (1088, swept in
-    global memory), in one batch call: each result equals the oracle's run
-    of that lattice alone."""
+    """A resident batch with fewer lattices than workgroups: sides up to 256
+    are held as bytes, the largest sides that fit local memory only as bits
+    (1072, 1080) bit-packed, and one that fits neither (1088) is swept in
+    global memory. J > 0, J < 0 and J = 0, thresholds of 0 (T = 0.05), near 1
+    (T = 50) and at T_c, in one batch call: each result equals the oracle's
+    run of that lattice alone."""
     runs = [W.Run(L=8, J=1.0, T=2.269185, seed=1, p_up=0.5, sweeps=40),
             W.Run(L=24, J=-1.0, T=2.0, seed=2, p_up=0.5, sweeps=30),
             W.Run(L=40, J=1.0, T=0.05, seed=3, p_up=0.5, sweeps=20),
@@ -146,6 +146,37 @@ def test_batch_bit_packed_couplings_and_sides(b, o):
         G.log(f"bit-packed batch: L={r.L} J={r.J} T={r.T} vs oracle")
         G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r),
                       f"bit-packed L={r.L} J={r.J} T={r.T}")
+
+
+def test_batch_bit_packed_saturated_batch(b, o):
+    """A resident batch with more lattices (400) than the launch has
+    workgroups, so every h = 0 lattice that fits local memory as bits is
+    bit-packed, small ones included: sides with partial 32-site words (8 to
+    136 in steps of 8), J > 0, J < 0 and J = 0, thresholds of 0 (T = 0.05),
+    near 1 (T = 50) and at T_c, one to five sweeps, plus a few h != 0
+    lattices (held as bytes). Each result equals the oracle's run of that
+    lattice alone."""
+    rng = np.random.default_rng(2024)
+    Js = [1.0, -1.0, 0.0, 0.5, -2.0]
+    Ts = [0.05, 1.0, 2.269185, 3.5, 50.0]
+    runs = []
+    for k in range(400):
+        L = int(8 * rng.integers(1, 18))
+        h = 0.1 if k % 50 == 7 else 0.0
+        runs.append(W.Run(L=L, J=Js[k % 5], h=h, T=Ts[(k // 5) % 5], seed=1000 + k,
+                          p_up=float(rng.choice([0.5, 1.0])), sweeps=int(rng.integers(1, 6))))
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    try:
+        G.log("saturated bit-packed batch of 400 (RESIDENT)")
+        b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], b.ISING_BATCH_RESIDENT)
+        for r, ctx in zip(runs, ctxs):
+            obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            spins = b.ising_copy_spins(ctx, r.L)
+            G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r),
+                          f"saturated batch L={r.L} J={r.J} h={r.h} T={r.T} seed={r.seed}")
+    finally:
+        for ctx in ctxs:
+            b.ising_destroy(ctx)
 
 
 def test_batch_stepped_fused_walk_ragged_tiles(b, o):
