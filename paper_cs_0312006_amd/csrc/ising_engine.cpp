@@ -64,6 +64,8 @@ struct Engine {
     hipGraph_t fgraph = nullptr;
     hipGraphExec_t fexec = nullptr;
     uint32_t fslots = 0;  // waves of the fused walk resident on the GPU at once
+    int64_t* d_part = nullptr;  // (B, M) of every tile for each sweep of a replay
+    size_t part_bytes = 0;
 };
 
 constexpr uint32_t kSweepsPerReplay = 16;
@@ -116,6 +118,7 @@ hipError_t ensure_capacity(Engine& e, size_t count) {
     while (cap < count) cap *= 2;
     // one staging block, [hdr | mhdr | order | vbs | items], so that a call
     // stages its descriptors with a single copy
+    static_assert(sizeof(BatchHeader) <= 32 && sizeof(MultiHeader) <= 32, "staging block headers");
     const size_t off_order = 64;
     const size_t off_vbs = off_order + cap * sizeof(uint32_t);
     const size_t off_items = (off_vbs + (cap + 1) * sizeof(uint32_t) + 255) & ~(size_t)255;
@@ -200,7 +203,27 @@ hipError_t ensure_multi_graph(Engine& e) {
     return r;
 }
 
-// Capture G sweeps of the stepped plan's fused walk (one advance node + G launches).
+// Room for the fused walk's tile partials: G sweeps x `tiles` (B, M) pairs.
+// The buffer only grows; growing waits for the device, since a queued
+// replay may still write the old one.
+hipError_t ensure_partials(Engine& e, uint64_t tiles) {
+    const size_t need = (size_t)kSweepsPerReplay * tiles * 2 * sizeof(int64_t);
+    if (need <= e.part_bytes) return hipSuccess;
+    hipError_t r = hipDeviceSynchronize();
+    if (r != hipSuccess) return r;
+    e.staged_pending = false;
+    if (e.d_part) (void)hipFree(e.d_part);
+    e.d_part = nullptr;
+    e.part_bytes = 0;
+    size_t cap = (size_t)1 << 20;
+    while (cap < need) cap *= 2;
+    if ((r = hipMalloc(&e.d_part, cap)) != hipSuccess) return r;
+    e.part_bytes = cap;
+    return hipSuccess;
+}
+
+// Capture G sweeps of the stepped plan's fused walk (one advance node, G
+// launches, one reduce of the tile partials into the series).
 hipError_t ensure_fused_graph(Engine& e) {
     if (e.fexec) return hipSuccess;
     hipStream_t cap = nullptr;
@@ -333,6 +356,17 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         e.h_mhdr->total_vblocks = (uint32_t)vb;
         e.h_mhdr->s_base = 0u - kSweepsPerReplay;  // the graph's first node adds G
         e.h_mhdr->rows = rows;
+        e.h_mhdr->part = nullptr;
+        if (fused) {
+            if ((r = ensure_partials(e, vb)) != hipSuccess) {
+                if (r == hipErrorOutOfMemory) {
+                    (void)hipGetLastError();
+                    return ISING_ENOMEM;
+                }
+                return ctx_fail(ctxs[0], r, "engine: tile partials");
+            }
+            e.h_mhdr->part = e.d_part;
+        }
     }
 
     // order the launch after every context's earlier work
@@ -356,9 +390,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         r = ensure_graph(e, s);
         if (r == hipSuccess) r = hipGraphLaunch(e.exec, s);
     } else if (fused) {
-        // the sweeps add their tiles' (B, M) into series slots cleared here
-        r = launch_multi_fused_clear(e.d_items, (uint32_t)count, s);
-        if (r == hipSuccess) r = ensure_fused_graph(e);
+        r = ensure_fused_graph(e);
         const uint64_t replays = (max_n + kSweepsPerReplay - 1) / kSweepsPerReplay;
         for (uint64_t k = 0; r == hipSuccess && k < replays; ++k) r = hipGraphLaunch(e.fexec, s);
     } else {

@@ -136,6 +136,7 @@ struct MultiHeader {
     uint32_t total_vblocks;  // virtual blocks (fused walk: tiles) over all items
     uint32_t s_base;         // sweep base; the graph's first node adds G to it
     uint32_t rows;           // fused walk: rows per tile (8, 16 or 32)
+    int64_t* part;           // fused walk: (B, M) of every tile for each sweep of a replay
 };
 constexpr uint32_t kMultiChunksPerThread = 4;
 uint32_t multi_vblocks(uint32_t L, uint32_t cw);
@@ -145,12 +146,13 @@ hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_st
 // Stepped multi-lattice sweeps with the fused walk (ising_multi_fused.hip):
 // one launch per sweep over the tiles (hdr->rows rows by 128 words) of
 // every item, each lattice ping-ponging between p and q; vb_start[k] is item
-// k's first tile. Sides must satisfy L % 16 == 0.
+// k's first tile. Sides must satisfy L % 16 == 0. Each tile writes its
+// (B, M) to hdr->part (G x total tiles pairs, sweep-major), and the replay's
+// last node sums them per item into the series.
 bool multi_fused_supported(uint32_t L);
 uint32_t multi_fused_tiles(uint32_t L, uint32_t rows);
 // Waves of the fused walk resident at once on a GPU with `cus` compute units.
 uint32_t multi_fused_wave_slots(uint32_t cus);
-hipError_t launch_multi_fused_clear(const BatchItem* items, uint32_t n_items, hipStream_t s);
 hipError_t launch_multi_fused_graph_body(const BatchItem* items, const uint32_t* tile_start, MultiHeader* hdr,
                                          uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
 

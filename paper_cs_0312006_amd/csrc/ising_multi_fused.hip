@@ -13,8 +13,9 @@
 //     shorter: lanes past the lattice's last word shadow its last lane
 //     (their loads stay in range, nothing of theirs is stored or counted),
 //     and that lane takes its right neighbour from the edge word;
-//   - the per-sweep (B, M) of a lattice are summed over its tiles with 64-bit
-//     atomic adds into its series slot, which is cleared before the sweeps.
+//   - each tile writes its (B, M) to a partial slot of its own, and the last
+//     node of a replay sums them per lattice into the series (no atomics: a
+//     lattice of thousands of tiles would serialise them on one address).
 // The draws are keyed by (seed, sweep, colour, site) as everywhere else, so
 // the result is the same as any other schedule of the same sweeps.
 #include <hip/hip_runtime.h>
@@ -179,6 +180,7 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
     const uint32_t n_items = hdr->n_items, total = hdr->total_vblocks;
     const uint32_t sweep = hdr->s_base + s;
     const uint32_t rows = hdr->rows;
+    int64_t* __restrict__ part = hdr->part + 2ull * s * total;
     const uint32_t waves = gridDim.x * (kMfThreads / 64);
     for (uint32_t g0 = blockIdx.x * (kMfThreads / 64) + wv; g0 < total; g0 += waves) {
         const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
@@ -203,19 +205,44 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
         if (it.exact) mf_tile<true>(lt[wv], it, tx, ty, rows, sweep, b, m);
         else mf_tile<false>(lt[wv], it, tx, ty, rows, sweep, b, m);
         if (lane == 0) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep]), (unsigned long long)b);
-            atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep + 1]), (unsigned long long)m);
+            part[2ull * g] = b;
+            part[2ull * g + 1] = m;
         }
         // the next tile's table must not overwrite this one while lanes read it
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Clear the series slots item k's sweeps of this call will add into.
-__global__ void __launch_bounds__(256) k_multi_fused_clear(const BatchItem* __restrict__ items, uint32_t n_items) {
-    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+// Sum the tile partials of each item's sweeps of this replay into its
+// series: one wave per (item, sweep of the replay), grid-stride.
+__global__ void __launch_bounds__(256) k_multi_fused_reduce(const BatchItem* __restrict__ items,
+                                                            const uint32_t* __restrict__ tile_start,
+                                                            const MultiHeader* __restrict__ hdr, uint32_t g_sweeps) {
+    const uint32_t n_items = hdr->n_items, total = hdr->total_vblocks, s_base = hdr->s_base;
+    const int64_t* __restrict__ part = hdr->part;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+    const uint32_t pairs = n_items * g_sweeps;
+    for (uint32_t q = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); q < pairs; q += waves) {
+        const uint32_t k = q / g_sweeps, j = q - k * g_sweeps;
         const BatchItem& it = items[k];
-        for (uint32_t j = threadIdx.x; j < 2u * it.n; j += blockDim.x) it.series[j] = 0;
+        const uint32_t sweep = s_base + j;
+        if (sweep >= it.n) continue;
+        const int64_t* __restrict__ pj = part + 2ull * j * total;
+        int64_t b = 0, m = 0;
+        for (uint32_t g = tile_start[k] + lane; g < tile_start[k + 1]; g += 64u) {
+            b += pj[2ull * g];
+            m += pj[2ull * g + 1];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            b += __shfl_xor(b, off, 64);
+            m += __shfl_xor(m, off, 64);
+        }
+        if (lane == 0) {
+            it.series[2ull * sweep] = b;
+            it.series[2ull * sweep + 1] = m;
+        }
     }
 }
 
@@ -236,12 +263,6 @@ uint32_t multi_fused_wave_slots(uint32_t cus) {
     return cus * (uint32_t)per_cu * (kMfThreads / 64);
 }
 
-hipError_t launch_multi_fused_clear(const BatchItem* items, uint32_t n_items, hipStream_t s) {
-    if (n_items == 0) return hipSuccess;
-    k_multi_fused_clear<<<min(n_items, 1024u), 256, 0, s>>>(items, n_items);
-    return hipGetLastError();
-}
-
 __global__ void __launch_bounds__(64) k_multi_fused_advance(MultiHeader* hdr, uint32_t g) {
     if (threadIdx.x == 0 && blockIdx.x == 0) hdr->s_base += g;
 }
@@ -251,6 +272,7 @@ hipError_t launch_multi_fused_graph_body(const BatchItem* items, const uint32_t*
     k_multi_fused_advance<<<1, 64, 0, s>>>(hdr, sweeps_per_replay);
     for (uint32_t k = 0; k < sweeps_per_replay; ++k)
         k_multi_fused<<<grid, kMfThreads, 0, s>>>(items, tile_start, hdr, k);
+    k_multi_fused_reduce<<<grid, 256, 0, s>>>(items, tile_start, hdr, sweeps_per_replay);
     return hipGetLastError();
 }
 
