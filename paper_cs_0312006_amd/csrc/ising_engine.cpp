@@ -64,7 +64,7 @@ struct Engine {
     hipGraph_t fgraph = nullptr;
     hipGraphExec_t fexec = nullptr;
     uint32_t fslots = 0;  // waves of the fused walk resident on the GPU at once
-    int64_t* d_part = nullptr;  // (B, M) of every tile for each sweep of a replay
+    int64_t* d_part = nullptr;  // (B, M) of every tile / virtual block for each sweep of a replay
     size_t part_bytes = 0;
 };
 
@@ -186,7 +186,8 @@ hipError_t ensure_graph(Engine& e, hipStream_t s) {
     return r;
 }
 
-// Capture G sweeps of the stepped plan (one advance node + 2 G passes).
+// Capture G sweeps of the stepped plan (one advance node, 2 G passes, one
+// reduce of the block partials into the series).
 hipError_t ensure_multi_graph(Engine& e) {
     if (e.mexec) return hipSuccess;
     hipStream_t cap = nullptr;
@@ -203,7 +204,8 @@ hipError_t ensure_multi_graph(Engine& e) {
     return r;
 }
 
-// Room for the fused walk's tile partials: G sweeps x `tiles` (B, M) pairs.
+// Room for the stepped plans' partials: G sweeps x `tiles` (B, M) pairs
+// (one per tile of the fused walk or virtual block of the two-pass walk).
 // The buffer only grows; growing waits for the device, since a queued
 // replay may still write the old one.
 hipError_t ensure_partials(Engine& e, uint64_t tiles) {
@@ -356,17 +358,14 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         e.h_mhdr->total_vblocks = (uint32_t)vb;
         e.h_mhdr->s_base = 0u - kSweepsPerReplay;  // the graph's first node adds G
         e.h_mhdr->rows = rows;
-        e.h_mhdr->part = nullptr;
-        if (fused) {
-            if ((r = ensure_partials(e, vb)) != hipSuccess) {
-                if (r == hipErrorOutOfMemory) {
-                    (void)hipGetLastError();
-                    return ISING_ENOMEM;
-                }
-                return ctx_fail(ctxs[0], r, "engine: tile partials");
+        if ((r = ensure_partials(e, vb)) != hipSuccess) {
+            if (r == hipErrorOutOfMemory) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
             }
-            e.h_mhdr->part = e.d_part;
+            return ctx_fail(ctxs[0], r, "engine: partials");
         }
+        e.h_mhdr->part = e.d_part;
     }
 
     // order the launch after every context's earlier work

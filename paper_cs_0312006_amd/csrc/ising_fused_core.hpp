@@ -82,14 +82,19 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t rs, uint32_t off, cons
 //
 // RAGGED: the tile may end before lane 63; `is_last` marks the last lane
 // that holds words of the lattice, whose right neighbour is then `edge`
-// rather than the next lane's word.
-template <int CW, bool EXACT, int P, bool OBS, bool RAGGED = false>
+// rather than the next lane's word. PACKED: the wave holds several row
+// bands side by side; `is_first` marks a band's first lane, whose left
+// neighbour is then `edge` rather than the previous lane's word, and `edge`
+// is per lane (its band's).
+template <int CW, bool EXACT, int P, bool OBS, bool RAGGED = false, bool PACKED = false>
 __device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>& own, const Row<CW>& up,
                                               const Row<CW>& dn, const Row<CW>& same, uint32_t edge,
                                               const Row<CW>& xw, uint64_t m0row, uint32_t t, uint32_t c,
-                                              uint32_t k0, uint32_t k1, uint32_t& sad, bool is_last = false) {
+                                              uint32_t k0, uint32_t k1, uint32_t& sad, bool is_last = false,
+                                              bool is_first = false) {
     uint32_t nb = P ? from_right(same.v[0], edge) : from_left(same.v[CW - 1], edge);
     if (RAGGED && P && is_last) nb = edge;
+    if (PACKED && !P && is_first) nb = edge;
     Row<CW> out;
 #pragma unroll
     for (int w = 0; w < CW; ++w) {

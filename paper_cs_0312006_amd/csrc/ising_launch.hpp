@@ -136,12 +136,17 @@ struct MultiHeader {
     uint32_t total_vblocks;  // virtual blocks (fused walk: tiles) over all items
     uint32_t s_base;         // sweep base; the graph's first node adds G to it
     uint32_t rows;           // fused walk: rows per tile (8, 16 or 32)
-    int64_t* part;           // fused walk: (B, M) of every tile for each sweep of a replay
+    int64_t* part;           // (B, M) of every virtual block for each sweep of a replay (sweep-major)
 };
 constexpr uint32_t kMultiChunksPerThread = 4;
 uint32_t multi_vblocks(uint32_t L, uint32_t cw);
 hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_start, MultiHeader* hdr,
                                    uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
+// The last node of a stepped replay (either walk): item k's series entries
+// for the replay's sweeps = the sums of hdr->part over its virtual blocks
+// vb_start[k] .. vb_start[k + 1] - 1.
+hipError_t launch_multi_reduce(const BatchItem* items, const uint32_t* vb_start, const MultiHeader* hdr,
+                               uint32_t sweeps_per_replay, uint32_t grid, hipStream_t s);
 
 // Stepped multi-lattice sweeps with the fused walk (ising_multi_fused.hip):
 // one launch per sweep over the tiles (hdr->rows rows by 128 words) of
@@ -150,6 +155,40 @@ hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_st
 // (B, M) to hdr->part (G x total tiles pairs, sweep-major), and the replay's
 // last node sums them per item into the series.
 bool multi_fused_supported(uint32_t L);
+// Tiles of a side-L lattice at `rows` rows per tile: n_tx columns of up to
+// 128 words (the last may be narrower) by n_ty row bands. When the last
+// column is at most 32 lanes (64 words) wide, `pack` of its row bands share
+// one wave (pack * prow <= 64), so that a narrow lattice does not leave
+// most lanes of its waves idle; its bands are prow rows high (rows, or 16
+// when rows does not divide L), n_typ of them. Tile order: the full
+// columns' tiles (column-fastest), then the last column's packed tiles;
+// with pack == 1, column-fastest over all columns.
+struct MfLayout {
+    uint32_t n_tx, n_ty, pack, prow, n_typ, tiles;
+};
+__host__ __device__ inline MfLayout mf_layout(uint32_t L, uint32_t rows) {
+    MfLayout o;
+    const uint32_t Hw = L / 8u;
+    o.n_tx = (Hw + 127u) / 128u;
+    o.n_ty = (L + rows - 1u) / rows;
+    o.pack = 1u;
+    o.prow = rows;
+    o.n_typ = o.n_ty;
+    const uint32_t last_lanes = (Hw - (o.n_tx - 1u) * 128u) / 2u;
+    if (last_lanes <= 32u) {
+        const uint32_t pr = L % rows == 0u ? rows : 16u;  // sides are multiples of 16
+        const uint32_t nb = L / pr;
+        uint32_t pk = 64u / last_lanes < 64u / pr ? 64u / last_lanes : 64u / pr;
+        if (pk > nb) pk = nb;
+        if (pk > 1u) {
+            o.pack = pk;
+            o.prow = pr;
+            o.n_typ = nb;
+        }
+    }
+    o.tiles = (o.n_tx - 1u) * o.n_ty + (o.n_typ + o.pack - 1u) / o.pack;
+    return o;
+}
 uint32_t multi_fused_tiles(uint32_t L, uint32_t rows);
 // Waves of the fused walk resident at once on a GPU with `cus` compute units.
 uint32_t multi_fused_wave_slots(uint32_t cus);

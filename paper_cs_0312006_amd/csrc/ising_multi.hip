@@ -102,12 +102,7 @@ __global__ void __launch_bounds__(kMultiThreads) k_multi_pass(const BatchItem* _
             else multi_chunk<1>(lt, it, c, t, idx, c == 1, it.exact != 0, sad, ups);
             nw += it.cw;
         }
-        if (c == 0) {
-            if (local == 0 && threadIdx.x == 0) {
-                it.series[2 * sweep] = 0;
-                it.series[2 * sweep + 1] = 0;
-            }
-        } else {
+        if (c == 1) {
             int64_t b = 16 * (int64_t)nw - 2 * (int64_t)sad;
             int64_t m = 2 * (int64_t)ups - 8 * (int64_t)nw;
 #pragma unroll
@@ -127,8 +122,10 @@ __global__ void __launch_bounds__(kMultiThreads) k_multi_pass(const BatchItem* _
                     sb += acc[0][w];
                     sm += acc[1][w];
                 }
-                atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep]), (unsigned long long)sb);
-                atomicAdd(reinterpret_cast<unsigned long long*>(&it.series[2 * sweep + 1]), (unsigned long long)sm);
+                // this block's partial; the replay's last node sums them
+                int64_t* p = hdr->part + 2ull * ((uint64_t)s * total + vb);
+                p[0] = sb;
+                p[1] = sm;
             }
         }
     }
@@ -147,7 +144,9 @@ hipError_t launch_multi_graph_body(const BatchItem* items, const uint32_t* vb_st
         k_multi_pass<<<grid, kMultiThreads, 0, s>>>(items, vb_start, hdr, k, 0u);
         k_multi_pass<<<grid, kMultiThreads, 0, s>>>(items, vb_start, hdr, k, 1u);
     }
-    return hipGetLastError();
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    return launch_multi_reduce(items, vb_start, hdr, sweeps_per_replay, grid, s);
 }
 
 }  // namespace ising

@@ -210,6 +210,33 @@ def test_batch_stepped_fused_walk_ragged_tiles(b, o):
                       G.oracle_run(o, r, sweeps=r.sweeps + e), f"stepped fused L={r.L}")
 
 
+def test_batch_stepped_fused_walk_packed_columns_tall_tiles(b, o):
+    """A stepped batch with enough tiles (560 lattices, about 17000 tiles)
+    for the walk to use 32-row tiles, mixing the tile kinds: full 128-word
+    columns with ragged bottom tiles (1040, 2064), narrow last columns
+    packed several row bands to a wave with 32-row bands (512, 1056, 1088)
+    and with 16-row bands where 32 does not divide the side (48, 80, 144,
+    272, 496, 1040, 1072, 1104, 2064), lattices too wide to pack (528) and
+    too short to (16, 32); h = 0 and h != 0, J < 0. Two calls (2 then 1
+    sweeps): every lattice equals the oracle's run of it alone."""
+    sides = [1040, 1072, 1056, 528, 48, 80, 144, 272, 496, 512, 16, 32, 1088, 1104, 2064]
+    runs = [W.Run(L=sides[k % len(sides)], J=-1.0 if k % 7 == 3 else 1.0, h=0.05 if k % 3 == 1 else 0.0,
+                  T=1.5 + 0.01 * (k % 200), seed=5000 + k, p_up=0.5, sweeps=3) for k in range(560)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    try:
+        G.log("stepped fused walk: 560 lattices, 32-row tiles, packed columns")
+        b.ising_sweep_batch_plan(ctxs, [2] * len(runs), b.ISING_BATCH_STEPPED)
+        b.ising_sweep_batch_plan(ctxs, [1] * len(runs), b.ISING_BATCH_STEPPED)
+        for k, (r, ctx) in enumerate(zip(runs, ctxs)):
+            obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            spins = b.ising_copy_spins(ctx, r.L)
+            G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r),
+                          f"packed-column batch lattice {k} L={r.L} J={r.J} h={r.h}")
+    finally:
+        for ctx in ctxs:
+            b.ising_destroy(ctx)
+
+
 def test_batch_stepped_fused_walk_many_large_lattices(b):
     """A stepped batch of 48 lattices of 2048^2 (h = 0 and h = 0.05): tiles
     of fewer rows are used when the batch has too few tiles to fill the GPU
