@@ -1,15 +1,18 @@
-// Stepped multi-lattice sweeps: one launch per colour pass covers the
-// chunks of every lattice in a work list, so each lattice, small or large,
-// is spread over the whole GPU (the resident batch kernel gives each lattice
-// one workgroup instead). Used for batches whose lattices are too large or
-// too many for one workgroup each, and by the request server.
+// Stepped multi-lattice sweeps, one pass per colour: one launch per colour
+// pass covers the chunks of every lattice in a work list, so each lattice,
+// small or large, is spread over the whole GPU (the resident batch kernel
+// gives each lattice one workgroup instead). Used by the stepped batch plan
+// when some side is not a multiple of 16 (otherwise the one-pass walk of
+// ising_multi_fused.hip runs).
 //
 // Work list: items (BatchItem, as for the resident kernel) and, per item,
 // the first of its virtual blocks; a launch strides over all virtual
 // blocks. A graph of G sweeps (2 G passes) is captured once; its first node
 // advances the sweep base by G, so replaying it ceil(n / G) times runs n
 // sweeps with no host work between replays. Items with fewer sweeps than
-// the others simply skip the passes beyond their count.
+// the others simply skip the passes beyond their count. Each virtual block
+// writes its (B, M) partial of a sweep, and the replay's last node sums them
+// per item into the series.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
