@@ -147,6 +147,20 @@ int ising_sweep(ising_ctx* ctx, uint64_t n);
 int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int64_t* mag_series,
                       uint64_t capacity, uint32_t want);
 
+/* Start the read-back of a later ising_observables(ctx, ..., want) without
+ * waiting: enqueue on the context's stream the device-to-host copies of the
+ * pending series (whole) and, with ISING_OBS_HASH, of the lattice, into
+ * pinned host memory the context owns. The next ising_observables call
+ * waits for these copies and answers from them when no call has changed the
+ * lattice or the series since and `want` covers what it asks for; otherwise
+ * it discards them and reads back afresh. A caller that keeps more work
+ * queued behind this context's last sweep (a server stepping other
+ * requests) thereby waits only for that sweep: copies enqueued later would
+ * run after the work queued before them. Errors: EINVAL (NULL ctx, unknown
+ * want bits), ESTATE, EUNSUPPORTED (more than 64 MiB to read back: call
+ * ising_observables alone), ENOMEM, EDEVICE. */
+int ising_prefetch_observables(ising_ctx* ctx, uint32_t want);
+
 /* Copy the current lattice to host memory `host` of n >= L*L bytes in the
  * canonical layout (row-major int8, +1 / -1). Synchronises. */
 int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n);

@@ -86,6 +86,7 @@ SIGNATURES = {
     "ising_sweep": (C.c_int, [C.c_void_p, C.c_uint64]),
     "ising_observables": (C.c_int, [C.c_void_p, C.POINTER(ising_obs), C.c_void_p, C.c_void_p, C.c_uint64,
                                     C.c_uint32]),
+    "ising_prefetch_observables": (C.c_int, [C.c_void_p, C.c_uint32]),
     "ising_copy_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t]),
     "ising_load_spins": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_uint64]),
     "ising_sweep_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p]),
@@ -220,6 +221,17 @@ def ising_observables(ctx, want=0, capacity=None):
         n = obs.series_len
         bs, ms = bs[:n], ms[:n]
     return obs, bs, ms
+
+
+def ising_prefetch_observables(ctx, want):
+    """Start the read-back of a later ising_observables(ctx, want) without
+    waiting. Returns False when the library declines (too much to stage), in
+    which case ising_observables reads back on its own."""
+    rc = lib().ising_prefetch_observables(ctx, int(want))
+    if rc == ISING_EUNSUPPORTED:
+        return False
+    _check(rc, "ising_prefetch_observables", ctx)
+    return True
 
 
 def ising_copy_spins(ctx, L):

@@ -368,10 +368,14 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         e.h_mhdr->part = e.d_part;
     }
 
-    // order the launch after every context's earlier work
+    // order the launch after every context's earlier work. A context with
+    // no API call since an earlier launch of this engine ordered its stream
+    // after that launch has nothing newer on its stream than that launch,
+    // which the wait on the previous launch below already covers.
     for (size_t k = 0; k < count; ++k) {
         hipStream_t cs = ctxs[k]->stream;
         if (cs == s) continue;
+        if (e.launched && ctxs[k]->engine_seq == ctxs[k]->api_seq) continue;
         if ((r = hipEventRecord(e.order_ev, cs)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: record order");
         if ((r = hipStreamWaitEvent(s, e.order_ev, 0)) != hipSuccess)
             return ctx_fail(ctxs[k], r, "engine: wait order");
@@ -403,13 +407,15 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         return ctx_fail(ctxs[0], r, "engine: record done");
     e.launched = true;
     // and every context's later work after it
+    if ((r = hipEventRecord(e.order_ev, s)) != hipSuccess) return ctx_fail(ctxs[0], r, "engine: record after");
     for (size_t k = 0; k < count; ++k) {
         hipStream_t cs = ctxs[k]->stream;
-        if (cs == s) continue;
-        if ((r = hipEventRecord(e.order_ev, s)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: record after");
-        if ((r = hipStreamWaitEvent(cs, e.order_ev, 0)) != hipSuccess) return ctx_fail(ctxs[k], r, "engine: wait after");
+        if (cs != s && (r = hipStreamWaitEvent(cs, e.order_ev, 0)) != hipSuccess)
+            return ctx_fail(ctxs[k], r, "engine: wait after");
+        ctxs[k]->engine_seq = ctxs[k]->api_seq;
     }
     for (size_t k = 0; k < count; ++k) {
+        if (n[k]) ++ctxs[k]->gen;
         ctxs[k]->t += n[k];
         ctxs[k]->series_len += n[k];
         if (fused && (n[k] & 1u)) ctxs[k]->cur ^= 1;  // an odd number of ping-pong sweeps

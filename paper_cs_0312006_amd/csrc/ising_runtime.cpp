@@ -188,6 +188,7 @@ int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where) {
 static int ctx_enter(ising_ctx* ctx) {
     if (!ctx) return ISING_EINVAL;
     if (ctx->poisoned) return ISING_ESTATE;
+    ++ctx->api_seq;  // the stream may get work the batch engine has not seen
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return ctx_fail(ctx, e, "hipSetDevice");
     return ISING_OK;
@@ -218,12 +219,16 @@ int ctx_reserve_series(ising_ctx* ctx, uint64_t more) {
         (void)hipGetLastError();
         return ISING_ENOMEM;
     }
-    if (ctx->series_len) {
-        HIP_TRY(ctx, hipMemcpyAsync(fresh, ctx->series, ctx->series_len * 2 * sizeof(int64_t),
-                                    hipMemcpyDeviceToDevice, ctx->stream));
+    if (ctx->series) {
+        if (ctx->series_len) {
+            HIP_TRY(ctx, hipMemcpyAsync(fresh, ctx->series, ctx->series_len * 2 * sizeof(int64_t),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        // queued work may still write the old buffer (a first buffer needs
+        // no wait: nothing queued refers to it)
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->series);
     }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    if (ctx->series) (void)hipFree(ctx->series);
     ctx->series = fresh;
     ctx->series_cap = cap;
     return ISING_OK;
@@ -423,6 +428,7 @@ int ising_reset(ising_ctx* ctx, const ising_params* params) {
     ctx->cur = 0;
     ctx->t = 0;
     ctx->series_len = 0;
+    ++ctx->gen;
     const uint64_t pthr = (uint64_t)std::floor(params->p_up * 4294967296.0);
     HIP_TRY(ctx, launch_init(ctx_planes(ctx), (ctx->L % 8u) == 0u, (uint32_t)params->seed,
                              (uint32_t)(params->seed >> 32), pthr, ctx->stream));
@@ -444,6 +450,7 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
     if (ctx->plan.kind == ISING_PLAN_RESIDENT) return engine_run(&ctx, &n, 1, ctx->stream, false);
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
+    ++ctx->gen;
     int64_t* ser = ctx->series + 2 * ctx->series_len;
     switch (ctx->plan.kind) {
         case ISING_PLAN_FUSED: rc = sweep_fused(ctx, n, ser); break;
@@ -528,6 +535,7 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t) {
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     ctx->t = t;
     ctx->series_len = 0;
+    ++ctx->gen;
     return ISING_OK;
 }
 
@@ -558,6 +566,58 @@ static void* ctx_host_stage(ising_ctx* ctx, size_t bytes) {
     return fresh;
 }
 
+// Enqueue on the context's stream the copies ising_observables reads: the
+// whole pending series into `ser` when `full` (else the current (B, M): the
+// last series entry, or a fresh reduction when no sweep is pending) and,
+// with ISING_OBS_HASH, the canonical lattice bytes into `bytes`.
+static int enqueue_readback(ising_ctx* ctx, uint32_t want, bool full, int64_t* ser, uint8_t* bytes) {
+    const uint64_t len = ctx->series_len;
+    if (full) {
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series, 2 * len * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    } else if (len) {
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series + 2 * (len - 1), 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    } else {
+        HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->scratch, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    if (want & ISING_OBS_HASH) {
+        const int rc = ensure_canonical(ctx);
+        if (rc != ISING_OK) return rc;
+        const size_t N = (size_t)ctx->L * ctx->L;
+        HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(bytes, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    return ISING_OK;
+}
+
+int ising_prefetch_observables(ising_ctx* ctx, uint32_t want) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (want & ~(ISING_OBS_HASH | ISING_OBS_SERIES)) return ISING_EINVAL;
+    if (ctx->pre_state == 1) {
+        // the stage is about to be rewritten: the earlier read-back must land first
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->pre_state = 0;
+    const uint64_t len = ctx->series_len;
+    const bool full = (want & ISING_OBS_SERIES) && len;
+    const size_t ser_bytes = (full ? 2 * len : 2) * sizeof(int64_t);
+    const size_t hash_off = (ser_bytes + 255) & ~(size_t)255;
+    const size_t N = (size_t)ctx->L * ctx->L;
+    uint8_t* stage = static_cast<uint8_t*>(ctx_host_stage(ctx, (want & ISING_OBS_HASH) ? hash_off + N : ser_bytes));
+    if (!stage) return ISING_EUNSUPPORTED;
+    rc = enqueue_readback(ctx, want, full, reinterpret_cast<int64_t*>(stage), stage + hash_off);
+    if (rc != ISING_OK) return rc;
+    ctx->pre_state = 1;
+    ctx->pre_full = full;
+    ctx->pre_want = want;
+    ctx->pre_gen = ctx->gen;
+    ctx->pre_hash_off = hash_off;
+    return ISING_OK;
+}
+
 int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int64_t* mag_series,
                       uint64_t capacity, uint32_t want) {
     int rc = ctx_enter(ctx);
@@ -568,42 +628,50 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
     const size_t N = (size_t)ctx->L * ctx->L;
     const bool copy_series = (want & ISING_OBS_SERIES) && len && (bond_series || mag_series);
     const bool hash = (want & ISING_OBS_HASH) != 0;
-    const size_t ser_bytes = (copy_series ? 2 * len : 2) * sizeof(int64_t);
-    const size_t hash_off = (ser_bytes + 255) & ~(size_t)255;
-    // read back into the context's pinned stage when it fits, else into
-    // pageable memory
-    uint8_t* stage = static_cast<uint8_t*>(ctx_host_stage(ctx, hash ? hash_off + N : ser_bytes));
     std::vector<int64_t> ser_pageable;
     std::vector<uint8_t> bytes_pageable;
-    if (!stage) {
-        try {
-            ser_pageable.resize(ser_bytes / sizeof(int64_t));
-            if (hash) bytes_pageable.resize(N);
-        } catch (...) {
-            return ISING_ENOMEM;
+    int64_t* ser = nullptr;
+    uint8_t* bytes = nullptr;
+    bool full = copy_series;
+    if (ctx->pre_state == 1) {
+        // a prefetched read-back must land before the stage is read or reused
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->pre_state = 2;
+    }
+    if (ctx->pre_state == 2) {
+        // it answers this call if nothing changed since and it holds
+        // everything asked for (and keeps answering until something changes)
+        if (ctx->pre_gen == ctx->gen && (want & ~ctx->pre_want) == 0 && (!copy_series || ctx->pre_full)) {
+            uint8_t* stage = static_cast<uint8_t*>(ctx->host_stage);
+            ser = reinterpret_cast<int64_t*>(stage);
+            bytes = stage + ctx->pre_hash_off;
+            full = ctx->pre_full;
+        } else {
+            ctx->pre_state = 0;
         }
     }
-    int64_t* ser = stage ? reinterpret_cast<int64_t*>(stage) : ser_pageable.data();
-    uint8_t* bytes = stage ? stage + hash_off : bytes_pageable.data();
-    if (copy_series) {
-        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series, ser_bytes, hipMemcpyDeviceToHost, ctx->stream));
-    } else if (len) {
-        // the last series entry is the current lattice's (B, M)
-        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->series + 2 * (len - 1), ser_bytes, hipMemcpyDeviceToHost,
-                                    ctx->stream));
-    } else {
-        HIP_TRY(ctx, launch_observe(ctx_planes(ctx), ctx->scratch, ctx->stream));
-        HIP_TRY(ctx, hipMemcpyAsync(ser, ctx->scratch, ser_bytes, hipMemcpyDeviceToHost, ctx->stream));
-    }
-    if (hash) {
-        rc = ensure_canonical(ctx);
+    if (!ser) {
+        const size_t ser_bytes = (full ? 2 * len : 2) * sizeof(int64_t);
+        const size_t hash_off = (ser_bytes + 255) & ~(size_t)255;
+        // read back into the context's pinned stage when it fits, else into
+        // pageable memory
+        uint8_t* stage = static_cast<uint8_t*>(ctx_host_stage(ctx, hash ? hash_off + N : ser_bytes));
+        if (!stage) {
+            try {
+                ser_pageable.resize(ser_bytes / sizeof(int64_t));
+                if (hash) bytes_pageable.resize(N);
+            } catch (...) {
+                return ISING_ENOMEM;
+            }
+        }
+        ser = stage ? reinterpret_cast<int64_t*>(stage) : ser_pageable.data();
+        bytes = stage ? stage + hash_off : bytes_pageable.data();
+        rc = enqueue_readback(ctx, want, full, ser, bytes);
         if (rc != ISING_OK) return rc;
-        HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
-        HIP_TRY(ctx, hipMemcpyAsync(bytes, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const uint64_t hsh = hash ? fnv1a64(bytes, N) : 0;
-    const int64_t* last = copy_series ? ser + 2 * (len - 1) : ser;
+    const int64_t* last = full ? ser + 2 * (len - 1) : ser;
     const int64_t bm[2] = {last[0], last[1]};
     if (copy_series) {
         for (uint64_t k = 0; k < len; ++k) {
@@ -622,7 +690,10 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
         out->lattice_hash = hsh;
         out->series_len = len;
     }
-    if (want & ISING_OBS_SERIES) ctx->series_len = 0;
+    if (want & ISING_OBS_SERIES) {
+        ctx->series_len = 0;
+        ++ctx->gen;
+    }
     return ISING_OK;
 }
 
@@ -798,6 +869,7 @@ int ising_creutz_init(ising_ctx* ctx, const uint8_t* host, size_t n, uint8_t fil
         HIP_TRY(ctx, launch_fill_u8(ctx->demon, N, fill, ctx->stream));
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ++ctx->gen;
     return ISING_OK;
 }
 
@@ -869,6 +941,7 @@ int ising_creutz_sweep(ising_ctx* ctx, uint64_t n, int reverse) {
     if (n == 0) return ISING_OK;
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
+    ++ctx->gen;
     int64_t* ser = ctx->series + 2 * ctx->series_len;
     uint32_t cw = 0, rows = 0;
     if (!reverse && ctx->L % 8u == 0u && default_fused(ctx->L, &cw, &rows)) {

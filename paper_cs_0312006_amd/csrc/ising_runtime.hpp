@@ -47,6 +47,16 @@ struct ising_ctx {
     int8_t* canon = nullptr;     // N bytes, canonical layout staging
     void* host_stage = nullptr;  // pinned host memory the observables are read back into
     size_t host_stage_bytes = 0;
+    uint64_t gen = 0;            // bumped by every call that changes the lattice or the series
+    uint64_t api_seq = 0;        // bumped by every API call on the context (ctx_enter)
+    uint64_t engine_seq = ~0ull;  // api_seq when the batch engine last ordered the stream after its launch
+    // a read-back started by ising_prefetch_observables into host_stage:
+    // 0 none, 1 copies enqueued, 2 copies landed (valid while gen == pre_gen)
+    int pre_state = 0;
+    bool pre_full = false;       // the whole series was copied (else only the current (B, M))
+    uint32_t pre_want = 0;
+    uint64_t pre_gen = 0;
+    size_t pre_hash_off = 0;
     uint8_t* demon = nullptr;    // Creutz demons (N bytes, colour-plane layout), once initialised
     uint8_t* demon_alt = nullptr;  // second demon buffer for the fused (ping-pong) Creutz sweep
     int64_t* cpart = nullptr;    // Creutz per-block (B, M) partials

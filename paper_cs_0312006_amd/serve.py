@@ -19,8 +19,10 @@ the GPU with.
 
 Up to `depth` epochs are enqueued before the oldest one is waited for:
 which requests take part and how many sweeps each runs is known in
-advance, and every request has its own stream, so retiring a request
-waits only for the epochs it was part of.
+advance, and every request has its own stream. A request's results are
+read back by copies enqueued right behind its last epoch (the executor's
+prefetch), so retiring it waits for that epoch only, not for the epochs
+enqueued after it.
 """
 import collections
 import math
@@ -88,6 +90,13 @@ class GpuExecutor:
     def step(self, handles, sweeps):
         self.b.ising_sweep_batch_plan(handles, sweeps, self.b.ISING_BATCH_STEPPED)
 
+    def prefetch(self, handle):
+        """Start reading back a request's results as soon as its last epoch
+        is enqueued, so that result() waits for that epoch only and not for
+        the epochs enqueued after it."""
+        b = self.b
+        b.ising_prefetch_observables(handle, b.ISING_OBS_SERIES | (b.ISING_OBS_HASH if self.hash_results else 0))
+
     def result(self, handle, run):
         b = self.b
         want = b.ISING_OBS_SERIES | (b.ISING_OBS_HASH if self.hash_results else 0)
@@ -128,6 +137,7 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=6
     epochs = 0
     t0 = clock()
     in_flight = collections.deque()            # (ids, sweeps) of enqueued epochs not yet retired, oldest first
+    prefetch = getattr(executor, "prefetch", None)
 
     def now():
         return clock() - t0
@@ -184,6 +194,11 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=6
             executor.step([active[r][0] for r in ids], sweeps)
             epochs += 1
             in_flight.append((ids, sweeps))
+            if prefetch:
+                # requests whose last sweeps are in this epoch
+                for rid, n in zip(ids, sweeps):
+                    if active[rid][1] - pending[rid] == n:
+                        prefetch(active[rid][0])
         # retire the oldest epoch once `depth` are queued behind it, or when
         # nothing new could be enqueued
         if in_flight and (len(in_flight) > depth or not ids):

@@ -166,6 +166,51 @@ def test_reset_equals_create_and_rejects_other_sides(b, o):
         b.ising_destroy(ctx)
 
 
+def test_prefetched_observables_equal_plain_ones(b, o):
+    """ising_prefetch_observables stages a read-back that the next
+    ising_observables answers from: the same series, sums and hash as a
+    plain call (oracle); a call asking for nothing leaves it for the next;
+    asking for more than was staged (the hash) or changing the lattice after
+    the prefetch (more sweeps, a reset) makes the call read back afresh."""
+    run = W.Run(L=64, J=1.0, h=0.05, T=2.0, seed=21, p_up=0.5, sweeps=11)
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    try:
+        both = b.ISING_OBS_SERIES | b.ISING_OBS_HASH
+        b.ising_sweep(ctx, 5)
+        assert b.ising_prefetch_observables(ctx, both)
+        b.ising_sweep(ctx, 6)  # changes the lattice: the staged copy is stale
+        obs0, _, _ = b.ising_observables(ctx, 0)  # asks for nothing; sizes the series
+        assert obs0.series_len == 11
+        assert b.ising_prefetch_observables(ctx, both)
+        obs1, _, _ = b.ising_observables(ctx, 0)  # answered from the stage, which stays
+        obs, B, M = b.ising_observables(ctx, both)
+        ref = G.oracle_run(o, run)
+        G.assert_same({"spins": b.ising_copy_spins(ctx, run.L), "B": B, "M": M, "hash": obs.lattice_hash},
+                      ref, "prefetched")
+        assert (obs1.bond_sum, obs1.mag_sum) == (int(B[-1]), int(M[-1]))
+        # staged without the hash, asked with it: read back afresh
+        b.ising_sweep(ctx, 4)
+        assert b.ising_prefetch_observables(ctx, b.ISING_OBS_SERIES)
+        obs2, B2, M2 = b.ising_observables(ctx, both)
+        ref2 = G.oracle_run(o, run, sweeps=15)
+        assert np.array_equal(B2, ref2["B"][11:]) and np.array_equal(M2, ref2["M"][11:])
+        assert obs2.lattice_hash == ref2["hash"]
+        # a reset after the prefetch: the next call sees the new lattice
+        b.ising_sweep(ctx, 2)
+        assert b.ising_prefetch_observables(ctx, both)
+        run3 = W.Run(L=64, J=-1.0, h=0.0, T=3.0, seed=5, p_up=1.0, sweeps=3)
+        b.ising_reset(ctx, run3.L, run3.J, run3.h, run3.T, run3.seed, run3.p_up)
+        b.ising_sweep(ctx, run3.sweeps)
+        obs3, B3, M3 = b.ising_observables(ctx, both)
+        G.assert_same({"spins": b.ising_copy_spins(ctx, 64), "B": B3, "M": M3, "hash": obs3.lattice_hash},
+                      G.oracle_run(o, run3), "after reset")
+        with pytest.raises(b.IsingError) as e:
+            b.ising_prefetch_observables(ctx, 4)
+        assert e.value.code == b.ISING_EINVAL
+    finally:
+        b.ising_destroy(ctx)
+
+
 def test_sweep_index_limit(b):
     ctx = b.ising_create(16)
     b.ising_load_spins(ctx, np.ones((16, 16), dtype=np.int8), 2 ** 32 - 2)
