@@ -143,3 +143,32 @@ def test_idle_server_sleeps_until_next_arrival():
     assert stats["makespan_s"] >= max(r.arrival for r in reqs)
     for r in res:
         assert r.latency == pytest.approx(0.0, abs=1e-9)
+
+
+class PrefetchingExecutor(FakeExecutor):
+    """Records when each request's read-back is started."""
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.prefetched = {}   # handle -> sweeps enqueued when prefetched
+
+    def prefetch(self, handle):
+        assert handle in self.live and handle not in self.prefetched, "prefetched twice"
+        self.prefetched[handle] = self.done[handle]
+
+    def result(self, handle, run):
+        assert self.prefetched.get(handle) == run.sweeps, "read-back not started right after its last epoch"
+        return super().result(handle, run)
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_read_back_starts_right_after_the_last_epoch(depth):
+    """With an executor that can prefetch, every request's read-back is
+    started once, right after the epoch holding its last sweeps is enqueued
+    (all its sweeps enqueued, none after), whatever the queue depth."""
+    clk = FakeClock()
+    ex = PrefetchingExecutor(clk)
+    reqs = _stream(n=60)
+    res, _ = serve.serve(reqs, ex, epoch_sweeps=32, clock=clk, sleep=clk.sleep, depth=depth)
+    assert len(res) == len(reqs) and all(not r.error for r in res)
+    assert len(ex.prefetched) == len(reqs)
