@@ -198,7 +198,7 @@ bool fused_supported(uint32_t L, uint32_t cw, uint32_t rows) {
     if (L % 8u != 0u) return false;
     const uint32_t Hw = L / 8u;
     if (cw != 1 && cw != 2 && cw != 4) return false;
-    if (rows != 8 && rows != 16 && rows != 32 && rows != 64) return false;
+    if (rows != 4 && rows != 8 && rows != 16 && rows != 32 && rows != 64) return false;
     return Hw % (64u * cw) == 0u && L % rows == 0u && L >= 4u;
 }
 
@@ -216,9 +216,10 @@ hipError_t launch_fused(const FusedArgs& a, const AcceptTable& at, bool exact, u
             launch_fused_t<CWv, Rv, false>(a, at, red, s);              \
         return hipGetLastError();                                       \
     }
-    ISING_FUSED_CASE(1, 8) ISING_FUSED_CASE(1, 16) ISING_FUSED_CASE(1, 32) ISING_FUSED_CASE(1, 64)
-    ISING_FUSED_CASE(2, 8) ISING_FUSED_CASE(2, 16) ISING_FUSED_CASE(2, 32) ISING_FUSED_CASE(2, 64)
-    ISING_FUSED_CASE(4, 8) ISING_FUSED_CASE(4, 16) ISING_FUSED_CASE(4, 32) ISING_FUSED_CASE(4, 64)
+    ISING_FUSED_CASE(1, 4) ISING_FUSED_CASE(1, 8) ISING_FUSED_CASE(1, 16) ISING_FUSED_CASE(1, 32)
+    ISING_FUSED_CASE(1, 64) ISING_FUSED_CASE(2, 4) ISING_FUSED_CASE(2, 8) ISING_FUSED_CASE(2, 16)
+    ISING_FUSED_CASE(2, 32) ISING_FUSED_CASE(2, 64) ISING_FUSED_CASE(4, 4) ISING_FUSED_CASE(4, 8)
+    ISING_FUSED_CASE(4, 16) ISING_FUSED_CASE(4, 32) ISING_FUSED_CASE(4, 64)
 #undef ISING_FUSED_CASE
     return hipErrorInvalidValue;
 }

@@ -754,7 +754,7 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
         cands.push_back(pl);
     } else {
         static const uint32_t cws[3] = {1, 2, 4};
-        static const uint32_t rs[4] = {8, 16, 32, 64};
+        static const uint32_t rs[5] = {4, 8, 16, 32, 64};
         for (uint32_t cw : cws)
             for (uint32_t r : rs)
                 if (plan_for(L, ISING_PLAN_FUSED, cw, r, &pl)) cands.push_back(pl);

@@ -314,7 +314,7 @@ def test_c1_4096_full_length(b, o, k):
         assert abs(e.mean() - physics.kaufman_energy(run.L, run.T)) < 0.03
 
 
-FUSED_SHAPES = [(cw, rows) for cw in (1, 2, 4) for rows in (8, 16, 32, 64)]
+FUSED_SHAPES = [(cw, rows) for cw in (1, 2, 4) for rows in (4, 8, 16, 32, 64)]
 
 
 @pytest.mark.parametrize("L", [8192, 16384])

@@ -44,7 +44,7 @@ def test_fused_every_tile_shape(b, o, L, h, T):
     ref = G.oracle_run(o, run)
     tried = 0
     for cw in (1, 2, 4):
-        for rows in (8, 16, 32, 64):
+        for rows in (4, 8, 16, 32, 64):
             if (L // 8) % (64 * cw) != 0:
                 continue
             G.log(f"fused L={L} cw={cw} rows={rows} h={h} T={T}")
