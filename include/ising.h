@@ -220,7 +220,7 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
 
 /* Force the plan of a context (ISING_PLAN_*; for ISING_PLAN_FUSED also the
  * chunk width cw in {1, 2, 4} words per lane and the tile height rows in
- * {8, 16, 32, 64}; 0 picks a default). Switching to the fused plan may
+ * {4, 8, 16, 32, 64}; 0 picks a default). Switching to the fused plan may
  * allocate a second lattice buffer. Results do not depend on the plan.
  * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
