@@ -540,8 +540,8 @@ def main():
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -56,7 +56,7 @@ extern "C" {
 #define ISING_ENOMEM (-2)      /* device or host allocation failed */
 #define ISING_EDEVICE (-3)     /* a HIP call failed; the context is now poisoned */
 #define ISING_ERANGE (-4)      /* sweep index would pass 2^32 - 1, or a buffer is too small */
-#define ISING_EUNSUPPORTED (-5) /* valid request this build cannot serve */
+#define ISING_EUNSUPPORTED (-5) /* valid request the library cannot serve */
 #define ISING_ESTATE (-6)      /* context poisoned by an earlier device error */
 
 #define ISING_MAX_L 65536u     /* counter word 0 holds site/8: L*L/8 must fit 32 bits */

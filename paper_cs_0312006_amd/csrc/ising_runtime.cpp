@@ -1033,7 +1033,7 @@ const char* ising_strerror(int code) {
         case ISING_ENOMEM: return "out of memory";
         case ISING_EDEVICE: return "HIP device error";
         case ISING_ERANGE: return "out of range";
-        case ISING_EUNSUPPORTED: return "unsupported by this build";
+        case ISING_EUNSUPPORTED: return "unsupported by this library";
         case ISING_ESTATE: return "context poisoned by an earlier device error";
         default: return "unknown error";
     }
