@@ -64,6 +64,7 @@ struct Engine {
     hipGraph_t fgraph = nullptr;
     hipGraphExec_t fexec = nullptr;
     uint32_t fslots = 0;  // waves of the fused walk resident on the GPU at once
+    uint32_t fgrid = 0;   // workgroups per launch of the fused walk
     int64_t* d_part = nullptr;  // (B, M) of every tile / virtual block for each sweep of a replay
     size_t part_bytes = 0;
 };
@@ -164,6 +165,12 @@ hipError_t init_engine(Engine& e) {
     e.grid = (uint32_t)prop.multiProcessorCount * (uint32_t)per_cu;
     e.mgrid = (uint32_t)prop.multiProcessorCount * 8u;
     e.fslots = multi_fused_wave_slots((uint32_t)prop.multiProcessorCount);
+    // the fused walk's launches: four times the workgroups the GPU holds at
+    // once (as many workgroups as it holds waves), so that most workgroups
+    // start as others finish and take about one tile per wave, rather than
+    // each resident wave striding over a fixed share of tiles that differ
+    // in height and width
+    e.fgrid = e.fslots;
     e.ready = true;
     return hipSuccess;
 }
@@ -233,7 +240,7 @@ hipError_t ensure_fused_graph(Engine& e) {
     if (r != hipSuccess) return r;
     r = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (r == hipSuccess) {
-        hipError_t lr = launch_multi_fused_graph_body(e.d_items, e.d_vbs, e.d_mhdr, kSweepsPerReplay, e.mgrid, cap);
+        hipError_t lr = launch_multi_fused_graph_body(e.d_items, e.d_vbs, e.d_mhdr, kSweepsPerReplay, e.fgrid, cap);
         r = hipStreamEndCapture(cap, &e.fgraph);
         if (lr != hipSuccess) r = lr;
     }
