@@ -63,12 +63,12 @@ PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
 PROFILED_MULTI_FUSED_SOURCES = "daa700dc20157e80"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
-                        "valu_lane_ops_per_attempt": 123095414.0 * 64 / 388630784,
-                        "valu_busy_rocprof": 0.753,
+                        "valu_lane_ops_per_attempt": 123302633.0 * 64 / 388630784,
+                        "valu_busy_rocprof": 0.769,
                         # share of the tiles' lane slots that hold lattice words
                         # in this configuration (narrow columns packed)
                         "lanes_on_lattice_words": 0.766,
-                        "hbm_bytes_per_sweep": (266689.7 * 2.0 + 383113.4) * 1024}
+                        "hbm_bytes_per_sweep": (269308.2 * 2.0 + 382538.4) * 1024}
 
 
 def batched_roofline(res, stepped):
