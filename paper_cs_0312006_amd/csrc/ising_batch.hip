@@ -351,6 +351,45 @@ __device__ __forceinline__ void run_any(const LdsTable& lt, const BatchItem& it,
     else run_lattice<1, EXACT>(lt, it, p0, p1, red);
 }
 
+// Every sweep of one lattice, by the whole workgroup: bit-packed in LDS,
+// as bytes in LDS, or in global memory (see the resident plan's notes).
+__device__ __forceinline__ void batch_one(const BatchItem& it, LdsTable& lt, uint32_t* lat,
+                                          uint32_t (*red)[kMaxWaves][2]) {
+    load_table(lt, it.table);
+    __syncthreads();
+    const uint32_t plane_words = it.L * it.Hw;
+    const uint32_t bit_words = it.L * ((it.Hw + 7u) / 8u);
+    if (it.bits && 2u * bit_words * 4u <= kBatchBitsLdsBytes && it.n > 0) {
+        bits_load(lat, it, (it.Hw + 7u) / 8u);
+        __syncthreads();
+        run_bits(lat, it, red);
+        __syncthreads();
+        bits_store(lat, it, (it.Hw + 7u) / 8u);
+    } else if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
+        uint32_t* l0 = lat;
+        uint32_t* l1 = lat + plane_words;
+        const global_u32* g0 = as_global(it.p0);
+        const global_u32* g1 = as_global(it.p1);
+        for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
+            l0[k] = g0[k];
+            l1[k] = g1[k];
+        }
+        __syncthreads();
+        if (it.exact) run_any<true>(lt, it, l0, l1, red);
+        else run_any<false>(lt, it, l0, l1, red);
+        __syncthreads();
+        global_u32* g0w = as_global(it.p0);
+        global_u32* g1w = as_global(it.p1);
+        for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
+            g0w[k] = l0[k];
+            g1w[k] = l1[k];
+        }
+    } else {
+        if (it.exact) run_any<true>(lt, it, as_global(it.p0), as_global(it.p1), red);
+        else run_any<false>(lt, it, as_global(it.p0), as_global(it.p1), red);
+    }
+}
+
 __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __restrict__ items,
                                                          const uint32_t* __restrict__ order, BatchHeader* hdr) {
     __shared__ LdsTable lt;
@@ -365,43 +404,20 @@ __global__ void __launch_bounds__(kBatchThreads) k_batch(const BatchItem* __rest
         // the same for every thread: keep it (and the item's fields) scalar
         const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_slot);
         if (slot >= count) break;
-        const BatchItem& it = items[order[slot]];
-        load_table(lt, it.table);
-        __syncthreads();
-        const uint32_t plane_words = it.L * it.Hw;
-        const uint32_t bit_words = it.L * ((it.Hw + 7u) / 8u);
-        if (it.bits && 2u * bit_words * 4u <= kBatchBitsLdsBytes && it.n > 0) {
-            bits_load(lat, it, (it.Hw + 7u) / 8u);
-            __syncthreads();
-            run_bits(lat, it, red);
-            __syncthreads();
-            bits_store(lat, it, (it.Hw + 7u) / 8u);
-        } else if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
-            uint32_t* l0 = lat;
-            uint32_t* l1 = lat + plane_words;
-            const global_u32* g0 = as_global(it.p0);
-            const global_u32* g1 = as_global(it.p1);
-            for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
-                l0[k] = g0[k];
-                l1[k] = g1[k];
-            }
-            __syncthreads();
-            if (it.exact) run_any<true>(lt, it, l0, l1, red);
-            else run_any<false>(lt, it, l0, l1, red);
-            __syncthreads();
-            global_u32* g0w = as_global(it.p0);
-            global_u32* g1w = as_global(it.p1);
-            for (uint32_t k = threadIdx.x; k < plane_words; k += blockDim.x) {
-                g0w[k] = l0[k];
-                g1w[k] = l1[k];
-            }
-        } else {
-            if (it.exact) run_any<true>(lt, it, as_global(it.p0), as_global(it.p1), red);
-            else run_any<false>(lt, it, as_global(it.p0), as_global(it.p1), red);
-        }
+        batch_one(items[order[slot]], lt, lat, red);
         // everyone has read s_slot and the table before they are replaced
         __syncthreads();
     }
+}
+
+// One lattice whose descriptor is the kernel argument: the resident plan of
+// a single context, with no descriptor staging, work queue or idle
+// workgroups.
+__global__ void __launch_bounds__(kBatchThreads) k_batch_one(const BatchItem it) {
+    __shared__ LdsTable lt;
+    __shared__ uint32_t red[kFlush][kMaxWaves][2];
+    __shared__ uint32_t lat[kBatchBitsLdsBytes / 4];
+    batch_one(it, lt, lat, red);
 }
 
 uint32_t bits_mode(const AcceptTable& at) {
@@ -433,6 +449,11 @@ uint32_t batch_block_threads() { return kBatchThreads; }
 
 hipError_t batch_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, (int)kBatchThreads, 0);
+}
+
+hipError_t launch_batch_one(const BatchItem& it, hipStream_t s) {
+    k_batch_one<<<1, kBatchThreads, 0, s>>>(it);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,

@@ -251,6 +251,29 @@ hipError_t ensure_fused_graph(Engine& e) {
 
 }  // namespace
 
+void fill_batch_item(const ising_ctx* c, uint64_t n, bool stepped, BatchItem& it) {
+    const Planes pl = ctx_planes(c);
+    it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
+    it.p1 = reinterpret_cast<uint32_t*>(pl.p[1]);
+    it.q0 = nullptr;
+    it.q1 = nullptr;
+    it.series = c->series + 2 * c->series_len;
+    it.L = c->L;
+    it.Hw = c->L / 8u;
+    it.cw = (it.Hw % 4u == 0u) ? 4u : (it.Hw % 2u == 0u) ? 2u : 1u;
+    // a lattice too small to give every thread of the resident workgroup a
+    // chunk uses one word per thread (latency, not width)
+    if (!stepped && (uint64_t)it.L * it.Hw <= 2ull * batch_block_threads()) it.cw = 1u;
+    it.t0 = (uint32_t)c->t;
+    it.n = (uint32_t)n;
+    it.k0 = (uint32_t)c->p.seed;
+    it.k1 = (uint32_t)(c->p.seed >> 32);
+    it.exact = c->exact ? 1u : 0u;
+    it.bits = 0u;
+    it.pad = 0;
+    it.table = c->table;
+}
+
 int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped) {
     int dev = ctxs[0]->device;
     if (dev < 0 || dev >= kMaxDevices) return ISING_EINVAL;
@@ -302,32 +325,14 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     const bool saturated = live >= e.grid;
     for (size_t k = 0; k < count; ++k) {
         ising_ctx* c = ctxs[k];
-        const Planes pl = ctx_planes(c);
         BatchItem& it = e.h_items[k];
-        it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
-        it.p1 = reinterpret_cast<uint32_t*>(pl.p[1]);
-        it.q0 = nullptr;
-        it.q1 = nullptr;
+        fill_batch_item(c, n[k], stepped, it);
         if (fused && c->buf[1]) {
             const Planes alt = ctx_planes_alt(c);
             it.q0 = reinterpret_cast<uint32_t*>(alt.p[0]);
             it.q1 = reinterpret_cast<uint32_t*>(alt.p[1]);
         }
-        it.series = c->series + 2 * c->series_len;
-        it.L = c->L;
-        it.Hw = c->L / 8u;
-        it.cw = (it.Hw % 4u == 0u) ? 4u : (it.Hw % 2u == 0u) ? 2u : 1u;
-        // a lattice too small to give every thread of the resident
-        // workgroup a chunk uses one word per thread (latency, not width)
-        if (!stepped && (uint64_t)it.L * it.Hw <= 2ull * batch_block_threads()) it.cw = 1u;
-        it.t0 = (uint32_t)c->t;
-        it.n = (uint32_t)n[k];
-        it.k0 = (uint32_t)c->p.seed;
-        it.k1 = (uint32_t)(c->p.seed >> 32);
-        it.exact = c->exact ? 1u : 0u;
         it.bits = (!stepped && bits_fit(c->L) && (saturated || !bytes_fit(c->L))) ? bits_mode(c->table) : 0u;
-        it.pad = 0;
-        it.table = c->table;
         work[k] = (uint64_t)c->L * c->L * n[k];
     }
     uint64_t max_n = 0;

@@ -127,6 +127,9 @@ bool bytes_fit(uint32_t L);
 
 hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHeader* hdr, uint32_t grid,
                         hipStream_t s);
+// One workgroup runs every sweep of the lattice `it` describes (passed by
+// value: nothing to stage).
+hipError_t launch_batch_one(const BatchItem& it, hipStream_t s);
 uint32_t batch_block_threads();
 hipError_t batch_occupancy(int* blocks_per_cu);
 

@@ -447,10 +447,20 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
     if (rc != ISING_OK) return rc;
     if (n == 0) return ISING_OK;
     if (ctx->t + n > ((uint64_t)1 << 32)) return ISING_ERANGE;
-    if (ctx->plan.kind == ISING_PLAN_RESIDENT) return engine_run(&ctx, &n, 1, ctx->stream, false);
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
     ++ctx->gen;
+    if (ctx->plan.kind == ISING_PLAN_RESIDENT) {
+        // one workgroup runs every sweep from local memory (bytes: a lone
+        // lattice's latency, not the chip's throughput, sets the time)
+        BatchItem it;
+        fill_batch_item(ctx, n, false, it);
+        if (bits_fit(ctx->L) && !bytes_fit(ctx->L)) it.bits = bits_mode(ctx->table);
+        HIP_TRY(ctx, launch_batch_one(it, ctx->stream));
+        ctx->t += n;
+        ctx->series_len += n;
+        return ISING_OK;
+    }
     int64_t* ser = ctx->series + 2 * ctx->series_len;
     switch (ctx->plan.kind) {
         case ISING_PLAN_FUSED: rc = sweep_fused(ctx, n, ser); break;

@@ -79,3 +79,8 @@ int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 // stream s, either as one persistent workgroup-resident launch or as the
 // stepped multi-lattice graph.
 int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped);
+// Descriptor of context c for n sweeps from its current state: lattice
+// planes, series slots after the pending ones, draw key, table, words per
+// thread (stepped or resident). The fused walk's second planes and the
+// bit-packing choice are left to the caller (null / 0).
+void fill_batch_item(const ising_ctx* c, uint64_t n, bool stepped, ising::BatchItem& it);
