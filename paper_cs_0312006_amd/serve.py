@@ -53,33 +53,38 @@ class Result:
 class GpuExecutor:
     """Executor over the C ABI (one stream per request).
 
-    Retired contexts are kept, up to `pool_per_side` of each side, and
-    re-initialised for later requests of that side (ising_reset) instead of
-    being freed and allocated again: freeing device memory synchronises the
-    device, which would drain the epochs queued behind it. Every context's
-    series is reserved at admission for at least `series_floor` sweeps (and
-    the whole request), so neither an epoch nor a reuse grows it. close()
-    releases the kept contexts."""
+    Retired contexts are kept, while their device bytes total at most
+    `pool_bytes`, and re-initialised for later requests of the same side
+    (ising_reset) instead of being freed and allocated again: freeing device
+    memory synchronises the device, which would drain the epochs queued
+    behind it. Every context's series is reserved at admission for at least
+    `series_floor` sweeps (and the whole request), so neither an epoch nor a
+    reuse grows it. close() releases the kept contexts."""
 
-    def __init__(self, hash_results=True, pool_per_side=8, series_floor=32768):
+    def __init__(self, hash_results=True, pool_bytes=8 << 30, series_floor=32768):
         from . import binding as b
         self.b = b
         b.lib()
         self.hash_results = hash_results
-        self.pool_per_side = pool_per_side
+        self.pool_bytes = pool_bytes      # device bytes of idle contexts kept for reuse, at most
+        self.pooled = 0                   # device bytes of the idle contexts now kept
         self.series_floor = series_floor  # every context's series holds at least this many sweeps
         self.pool = collections.defaultdict(list)  # side -> idle contexts
         self.side = {}                             # context -> side
 
-    def bytes_for(self, run):
+    def _bytes(self, L):
         # the stepped plan alternates a lattice between two buffers
-        return self.b.ising_state_bytes(run.L, self.b.ISING_PLAN_FUSED) or 2 * run.L * run.L
+        return self.b.ising_state_bytes(L, self.b.ISING_PLAN_FUSED) or 2 * L * L
+
+    def bytes_for(self, run):
+        return self._bytes(run.L)
 
     def create(self, run):
         b = self.b
         idle = self.pool.get(run.L)
         if idle:
             handle = idle.pop()
+            self.pooled -= self._bytes(run.L)
             b.ising_reset(handle, run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
         else:
             handle = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
@@ -108,8 +113,10 @@ class GpuExecutor:
 
     def destroy(self, handle):
         L = self.side[handle]
-        if len(self.pool[L]) < self.pool_per_side:
+        need = self._bytes(L)
+        if self.pooled + need <= self.pool_bytes:
             self.pool[L].append(handle)
+            self.pooled += need
         else:
             del self.side[handle]
             self.b.ising_destroy(handle)
@@ -120,6 +127,7 @@ class GpuExecutor:
                 self.b.ising_destroy(handle)
                 del self.side[handle]
         self.pool.clear()
+        self.pooled = 0
 
 
 def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=64,
