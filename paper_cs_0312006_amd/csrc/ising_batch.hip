@@ -451,6 +451,20 @@ hipError_t batch_occupancy(int* blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, (int)kBatchThreads, 0);
 }
 
+// Word copy from pinned host memory (read over the bus) to device memory.
+__global__ void __launch_bounds__(256) k_stage_copy(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                    uint32_t words) {
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < words; k += gridDim.x * blockDim.x) dst[k] = src[k];
+}
+
+hipError_t launch_stage_copy(void* dst, const void* host_src, size_t bytes, hipStream_t s) {
+    const uint32_t words = (uint32_t)(bytes / 4u);
+    if (words == 0) return hipSuccess;
+    const uint32_t blocks = min((words + 255u) / 256u, 64u);
+    k_stage_copy<<<blocks, 256, 0, s>>>(static_cast<uint32_t*>(dst), static_cast<const uint32_t*>(host_src), words);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_one(const BatchItem& it, hipStream_t s) {
     k_batch_one<<<1, kBatchThreads, 0, s>>>(it);
     return hipGetLastError();

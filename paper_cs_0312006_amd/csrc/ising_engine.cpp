@@ -395,7 +395,8 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     // the device descriptors may still be read by the previous launch
     if (e.launched && (r = hipStreamWaitEvent(s, e.done_relay, 0)) != hipSuccess)
         return ctx_fail(ctxs[0], r, "engine: wait previous launch");
-    r = hipMemcpyAsync(e.d_stage, e.h_stage, e.off_items + count * sizeof(BatchItem), hipMemcpyHostToDevice, s);
+    static_assert(sizeof(BatchItem) % 4 == 0, "staging copies whole words");
+    r = launch_stage_copy(e.d_stage, e.h_stage, e.off_items + count * sizeof(BatchItem), s);
     if (r != hipSuccess) return ctx_fail(ctxs[0], r, "engine: stage descriptors");
     if ((r = hipEventRecord(e.staged, s)) != hipSuccess || (r = hipStreamWaitEvent(e.relay, e.staged, 0)) != hipSuccess ||
         (r = hipEventRecord(e.staged_relay, e.relay)) != hipSuccess)

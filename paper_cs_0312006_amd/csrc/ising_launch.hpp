@@ -130,6 +130,11 @@ hipError_t launch_batch(const BatchItem* items, const uint32_t* order, BatchHead
 // One workgroup runs every sweep of the lattice `it` describes (passed by
 // value: nothing to stage).
 hipError_t launch_batch_one(const BatchItem& it, hipStream_t s);
+// Copy `bytes` (a multiple of 4) from pinned host memory to device memory
+// with a kernel on stream s: it starts as soon as the stream's earlier work
+// ends, where a copy-engine transfer waiting on another stream's event
+// started hundreds of microseconds later.
+hipError_t launch_stage_copy(void* dst, const void* host_src, size_t bytes, hipStream_t s);
 uint32_t batch_block_threads();
 hipError_t batch_occupancy(int* blocks_per_cu);
 
