@@ -172,13 +172,14 @@ int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n);
 int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
 
 /* Run n_sweeps[k] sweeps on ctxs[k], k < count, together on `stream`
- * (NULL: the first context's stream), with the batch plan ISING_BATCH_AUTO
+ * (NULL: the library's own stream on the contexts' device, which keeps
+ * consecutive batches in stream order), with the batch plan ISING_BATCH_AUTO
  * picks (see ising_sweep_batch_plan): one persistent launch from a captured
  * graph in which each workgroup takes whole lattices, largest work first,
  * and runs all of their sweeps from its local memory, or, when some lattice
  * is too large for that, graph replays of passes that spread every lattice
- * over the whole GPU. The descriptors are staged with one host-to-device
- * copy. Lattices may differ in L, J, h, T and seed; each must satisfy
+ * over the whole GPU. The descriptors are staged through pinned host
+ * memory by one copy kernel. Lattices may differ in L, J, h, T and seed; each must satisfy
  * L % 8 == 0 and have no pending device error. Contexts are validated
  * before anything is launched (all-or-nothing). The results are
  * bit-identical to calling ising_sweep on each context alone. Asynchronous;

@@ -49,6 +49,8 @@ struct Engine {
     hipEvent_t done_relay = nullptr;
     bool staged_pending = false;
     bool launched = false;
+    hipStream_t last_stream = nullptr;  // stream of the last launch (meaningful while launched)
+    hipStream_t launch = nullptr;  // the engine's own launch stream (calls that name none), never destroyed
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t grid = 0;
@@ -154,6 +156,8 @@ hipError_t init_engine(Engine& e) {
     r = hipEventCreateWithFlags(&e.done_relay, hipEventDisableTiming);
     if (r != hipSuccess) return r;
     r = hipStreamCreateWithFlags(&e.relay, hipStreamNonBlocking);
+    if (r != hipSuccess) return r;
+    r = hipStreamCreateWithFlags(&e.launch, hipStreamNonBlocking);
     if (r != hipSuccess) return r;
     int dev = 0;
     hipDeviceProp_t prop;
@@ -286,6 +290,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
     Engine& e = g_engines[dev];
     std::lock_guard<std::mutex> g(e.mu);
     hipError_t r = init_engine(e);
+    if (r == hipSuccess && !s) s = e.launch;
     if (r == hipSuccess) r = ensure_capacity(e, count);
     if (r != hipSuccess) {
         if (r == hipErrorOutOfMemory) {
@@ -392,8 +397,10 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         if ((r = hipStreamWaitEvent(s, e.order_ev, 0)) != hipSuccess)
             return ctx_fail(ctxs[k], r, "engine: wait order");
     }
-    // the device descriptors may still be read by the previous launch
-    if (e.launched && (r = hipStreamWaitEvent(s, e.done_relay, 0)) != hipSuccess)
+    // the device descriptors may still be read by the previous launch (when
+    // both are on the engine's own stream, stream order already waits for it)
+    const bool after_own = s == e.launch && e.last_stream == e.launch;
+    if (e.launched && !after_own && (r = hipStreamWaitEvent(s, e.done_relay, 0)) != hipSuccess)
         return ctx_fail(ctxs[0], r, "engine: wait previous launch");
     static_assert(sizeof(BatchItem) % 4 == 0, "staging copies whole words");
     r = launch_stage_copy(e.d_stage, e.h_stage, e.off_items + count * sizeof(BatchItem), s);
@@ -419,6 +426,7 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         (r = hipEventRecord(e.done_relay, e.relay)) != hipSuccess)
         return ctx_fail(ctxs[0], r, "engine: record done");
     e.launched = true;
+    e.last_stream = s;
     // and every context's later work after it
     if ((r = hipEventRecord(e.order_ev, s)) != hipSuccess) return ctx_fail(ctxs[0], r, "engine: record after");
     for (size_t k = 0; k < count; ++k) {

@@ -506,7 +506,7 @@ int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, siz
             if (c->L > kResidentBatchMaxL && !(bits_fit(c->L) && bits_mode(c->table) != 0)) stepped = true;
         }
     }
-    return engine_run(ctxs, n_sweeps, count, stream ? (hipStream_t)stream : ctxs[0]->stream, stepped);
+    return engine_run(ctxs, n_sweeps, count, static_cast<hipStream_t>(stream), stepped);
 }
 
 static int ensure_canonical(ising_ctx* ctx) {

@@ -78,6 +78,9 @@ int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 // Batch engine (ising_engine.cpp): run ctxs[k] for n[k] sweeps each on
 // stream s, either as one persistent workgroup-resident launch or as the
 // stepped multi-lattice graph.
+// Run a batch on stream s (nullptr: the engine's own stream on the
+// contexts' device), ordered after every context's earlier work and before
+// its later work.
 int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped);
 // Descriptor of context c for n sweeps from its current state: lattice
 // planes, series slots after the pending ones, draw key, table, words per
