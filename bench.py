@@ -534,7 +534,8 @@ def main():
     ap.add_argument("--epoch-sweeps", type=int, default=64)
     ap.add_argument("--creutz-sweeps", type=int, default=100)
     ap.add_argument("--only", default=None,
-                    choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped"],
+                    choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped",
+                             "served"],
                     help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
@@ -558,6 +559,8 @@ def main():
             leg = run_percolation(b, cpu=False)
         elif args.only == "percolation-media":
             leg = run_percolation(b, cpu=False, spanning=False)
+        elif args.only == "served":
+            leg = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
         elif args.only in ("batched", "batched-stepped"):
             leg, _ = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0,
                                  plan=0 if args.only == "batched" else 2)
