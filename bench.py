@@ -31,7 +31,7 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit op
 # timed plan is one of these; otherwise they are null. A recorded hash is
 # moved forward after a change elsewhere in these files only once the
 # profiled kernel is seen to compile to the same instructions.
-PROFILED_SOURCES = "3026eedec5faa191"
+PROFILED_SOURCES = "f9f355a75190fcc6"
 PROFILED = {
     # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch, mean of 54)
     "k_fused<4,32>": {"hbm_bytes_per_launch": (690127.8 * 2.0 + 1048863.4) * 1024,
@@ -46,7 +46,7 @@ PROFILED = {
 
 # Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md),
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch, mean of 22
-PROFILED_CREUTZ_SOURCES = "31c1d394f8cc629e"
+PROFILED_CREUTZ_SOURCES = "bfe59632a49acf68"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
                    "hbm_bytes_per_sweep": (1316828.2 * 2.0 + 2097585.8) * 1024}
 
@@ -56,12 +56,12 @@ PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
 # (profiles/k_multi_fused_batched_1024.md, mean per dispatch; FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 KiB)
 BATCH_FILES = ("ising_batch.hip", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_BATCH_SOURCES = "9cb0155ee6c4d903"
+PROFILED_BATCH_SOURCES = "30aa04fb478a53b9"
 PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
                   "valu_lane_ops_per_attempt": 192905879841.0 * 64 / (388630784 * 2000),
                   "valu_busy_rocprof": 0.951}
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_MULTI_FUSED_SOURCES = "bf5647206a6cefda"
+PROFILED_MULTI_FUSED_SOURCES = "deba87c1b56f686e"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
                         "valu_lane_ops_per_attempt": 123302633.0 * 64 / 388630784,
                         "valu_busy_rocprof": 0.769,
