@@ -179,6 +179,34 @@ def test_batch_bit_packed_saturated_batch(b, o):
             b.ising_destroy(ctx)
 
 
+def test_batches_alternate_between_named_and_own_streams(b, o):
+    """Consecutive batch calls on the same contexts, alternating between a
+    caller's stream and the library's own (no stream named), with both
+    plans: every call follows the previous one, and each result equals the
+    oracle's run of that lattice alone."""
+    import torch
+    runs = [W.Run(L=L, J=1.0, h=h, T=T, seed=40 + k, p_up=0.5, sweeps=0)
+            for k, (L, h, T) in enumerate([(64, 0.0, 2.269185), (96, 0.05, 1.8), (256, 0.0, 3.0), (528, -0.1, 2.2)])]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    side = torch.cuda.Stream()
+    calls = [(b.ISING_BATCH_STEPPED, side.cuda_stream, 5), (b.ISING_BATCH_RESIDENT, None, 3),
+             (b.ISING_BATCH_STEPPED, None, 4), (b.ISING_BATCH_RESIDENT, side.cuda_stream, 2),
+             (b.ISING_BATCH_STEPPED, None, 1)]
+    try:
+        total = 0
+        for plan, stream, n in calls:
+            G.log(f"alternating streams: plan {plan} stream {'named' if stream else 'own'} {n} sweeps")
+            b.ising_sweep_batch_plan(ctxs, [n] * len(runs), plan, stream=stream)
+            total += n
+        for r, ctx in zip(runs, ctxs):
+            obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            G.assert_same({"spins": b.ising_copy_spins(ctx, r.L), "B": B, "M": M, "hash": obs.lattice_hash},
+                          G.oracle_run(o, r, sweeps=total), f"alternating streams L={r.L}")
+    finally:
+        for ctx in ctxs:
+            b.ising_destroy(ctx)
+
+
 def test_batch_stepped_fused_walk_ragged_tiles(b, o):
     """The stepped plan's one-pass walk (every side a multiple of 16): sides
     whose tiles end before the last lane (plane rows of 2 to 258 words) and
