@@ -111,12 +111,12 @@ def host_cores():
         return os.cpu_count() or 1
 
 
-def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None):
+def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None, first=2):
     """Returns dict with timing, plan and the series of the first sweeps."""
     ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
     try:
         # first sweeps from the initial state, kept for the oracle cross-check
-        b.ising_sweep(ctx, 2)
+        b.ising_sweep(ctx, first)
         _, B0, M0 = b.ising_observables(ctx, b.ISING_OBS_SERIES)
         if force:
             b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, force[0], force[1])
@@ -523,7 +523,8 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="force the fused plan with this tile height")
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=8,
+                    help="oracle sweeps of the headline lattice for cpu_baseline (about 10 s on 16 cores)")
     ap.add_argument("--batched-sweeps", type=int, default=10000)
     ap.add_argument("--batched-sample", type=int, default=64)
     ap.add_argument("--no-served", action="store_true")
@@ -571,7 +572,8 @@ def main():
 
     run = W.C2_HEADLINE
     force = (args.cw, args.rows) if (args.cw or args.rows) else None
-    head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force)
+    head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force,
+                        first=max(2, args.cpu_sweeps))
     ms, steps = head["ms"], args.steps
     attempts = run.L * run.L * steps
     value = attempts / ms / 1e6  # attempts per ns
