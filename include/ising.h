@@ -150,15 +150,16 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
 /* Start the read-back of a later ising_observables(ctx, ..., want) without
  * waiting: enqueue on the context's stream the device-to-host copies of the
  * pending series (whole) and, with ISING_OBS_HASH, of the lattice, into
- * pinned host memory the context owns. The next ising_observables call
- * waits for these copies and answers from them when no call has changed the
- * lattice or the series since and `want` covers what it asks for; otherwise
- * it discards them and reads back afresh. A caller that keeps more work
- * queued behind this context's last sweep (a server stepping other
- * requests) thereby waits only for that sweep: copies enqueued later would
- * run after the work queued before them. Errors: EINVAL (NULL ctx, unknown
- * want bits), ESTATE, EUNSUPPORTED (more than 64 MiB to read back: call
- * ising_observables alone), ENOMEM, EDEVICE. */
+ * pinned host memory the context owns. Later ising_observables calls wait
+ * for these copies and answer from them as long as no call has changed the
+ * lattice or the series since (clearing the series is such a change) and
+ * `want` covers what they ask for; otherwise the copies are discarded and
+ * the call reads back afresh. A caller that keeps more work queued behind
+ * this context's last sweep (a server stepping other requests) thereby
+ * waits only for that sweep: copies enqueued later would run after the work
+ * queued before them. Errors: EINVAL (NULL ctx, unknown want bits), ESTATE,
+ * EUNSUPPORTED (more than 64 MiB to read back, or no pinned memory to be
+ * had: call ising_observables alone), EDEVICE. */
 int ising_prefetch_observables(ising_ctx* ctx, uint32_t want);
 
 /* Copy the current lattice to host memory `host` of n >= L*L bytes in the
