@@ -180,8 +180,9 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * and runs all of their sweeps from its local memory, or, when some lattice
  * is too large for that, graph replays of passes that spread every lattice
  * over the whole GPU. The descriptors are staged through pinned host
- * memory by one copy kernel. Lattices may differ in L, J, h, T and seed; each must satisfy
- * L % 8 == 0 and have no pending device error. Contexts are validated
+ * memory by one copy kernel. Lattices may differ in L, J, h, T and seed;
+ * each must satisfy L % 8 == 0 and have no pending device error. Contexts
+ * are validated
  * before anything is launched (all-or-nothing). The results are
  * bit-identical to calling ising_sweep on each context alone. Asynchronous;
  * the contexts' own streams are ordered after it. */
@@ -195,6 +196,8 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
  *   fewer lattices than the launch has workgroups, those of side up to 256
  *   are held as bytes (lower latency per sweep); other lattices of side up
  *   to 256 are held there as bytes; larger ones are swept in global memory;
+ *   (a single context's ising_sweep under the resident plan runs the same
+ *   per-lattice code in one workgroup, launched directly);
  * ISING_BATCH_STEPPED: every sweep is one launch over the tiles of all
  *   lattices, so each lattice is spread over the whole GPU; sweeps are
  *   replayed from a captured graph in groups of 16. When every side is a
