@@ -182,10 +182,9 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * over the whole GPU. The descriptors are staged through pinned host
  * memory by one copy kernel. Lattices may differ in L, J, h, T and seed;
  * each must satisfy L % 8 == 0 and have no pending device error. Contexts
- * are validated
- * before anything is launched (all-or-nothing). The results are
- * bit-identical to calling ising_sweep on each context alone. Asynchronous;
- * the contexts' own streams are ordered after it. */
+ * are validated before anything is launched (all-or-nothing). The results
+ * are bit-identical to calling ising_sweep on each context alone.
+ * Asynchronous; the contexts' own streams are ordered after it. */
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream);
 
 /* As ising_sweep_batch with an explicit batch plan:
