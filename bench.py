@@ -532,7 +532,8 @@ def main():
     ap.add_argument("--served-subsat-rate", type=float, default=10.0,
                     help="one extra, sub-saturation arrival rate (0: skip)")
     ap.add_argument("--served-requests", type=int, default=256)
-    ap.add_argument("--epoch-sweeps", type=int, default=64)
+    ap.add_argument("--epoch-sweeps", type=int, default=128,
+                    help="sweeps per request per server epoch (128 beat 64 by 1-3% in throughput and latency)")
     ap.add_argument("--creutz-sweeps", type=int, default=100)
     ap.add_argument("--only", default=None,
                     choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped",

@@ -130,7 +130,7 @@ class GpuExecutor:
         self.pooled = 0
 
 
-def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=64,
+def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=128,
           clock=time.perf_counter, sleep=time.sleep, depth=2):
     """Run a stream of workloads.Request through the executor. Returns
     (results sorted by request id, stats). Up to `depth` epochs are enqueued
