@@ -254,7 +254,7 @@ def run_small_configs(b, torch, stream):
     for run in [W.C0] + list(W.C1):
         ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
         try:
-            b.ising_tune(ctx, 10)
+            b.ising_tune(ctx, 50)
             plan = b.ising_plan_info(ctx)
             b.ising_observables(ctx, b.ISING_OBS_SERIES)
             torch.cuda.synchronize()
