@@ -209,6 +209,18 @@ def test_prefetched_observables_equal_plain_ones(b, o):
         assert e.value.code == b.ISING_EINVAL
     finally:
         b.ising_destroy(ctx)
+    # more than the 64 MiB staging limit (a 16384^2 lattice's canonical
+    # bytes): declined, and the plain read-back still answers
+    big = b.ising_create(16384, 1.0, 0.0, 2.269185, 3, 0.5)
+    try:
+        b.ising_sweep(big, 1)
+        assert not b.ising_prefetch_observables(big, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        assert b.ising_prefetch_observables(big, b.ISING_OBS_SERIES)
+        obs, B, M = b.ising_observables(big, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        assert len(B) == 1 and (int(B[0]), int(M[0])) == (obs.bond_sum, obs.mag_sum)
+        assert obs.lattice_hash == o.fnv1a64(b.ising_copy_spins(big, 16384))
+    finally:
+        b.ising_destroy(big)
 
 
 def test_sweep_index_limit(b):
