@@ -204,7 +204,11 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
  *   two buffers; a context without its second buffer gets one, L*L bytes,
  *   on first use); otherwise it is a launch per colour, in place;
  * ISING_BATCH_AUTO: resident when every lattice is held in local memory
- *   (side <= 256, or h = 0 and side <= 1072), else stepped.
+ *   (side <= 256, or h = 0 and side <= 1072) and either every side is at
+ *   most 256 or the resident launch keeps its workgroups (one per compute
+ *   unit) busy enough: its makespan, lattices handed out largest work
+ *   first, beats the stepped plan's time at 0.63 of the resident kernel's
+ *   whole-GPU rate; else stepped.
  * Results are identical for every plan. */
 #define ISING_BATCH_AUTO 0u
 #define ISING_BATCH_RESIDENT 1u

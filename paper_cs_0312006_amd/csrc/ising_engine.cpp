@@ -255,6 +255,17 @@ hipError_t ensure_fused_graph(Engine& e) {
 
 }  // namespace
 
+uint32_t engine_resident_slots(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return 0;
+    Engine& e = g_engines[dev];
+    std::lock_guard<std::mutex> g(e.mu);
+    if (init_engine(e) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return e.grid;
+}
+
 void fill_batch_item(const ising_ctx* c, uint64_t n, bool stepped, BatchItem& it) {
     const Planes pl = ctx_planes(c);
     it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);

@@ -82,6 +82,9 @@ int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 // contexts' device), ordered after every context's earlier work and before
 // its later work.
 int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped);
+// Workgroups of the persistent resident launch on device dev (lattices it
+// runs at once); 0 if the engine cannot be set up.
+uint32_t engine_resident_slots(int dev);
 // Descriptor of context c for n sweeps from its current state: lattice
 // planes, series slots after the pending ones, draw key, table, words per
 // thread (stepped or resident). The fused walk's second planes and the
