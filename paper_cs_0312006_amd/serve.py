@@ -5,10 +5,11 @@ lattice (J, h, T, seed, p_up) and gets back the final lattice hash, the
 final bond sum and magnetisation and FP64 averages of the per-sweep series.
 
 The loop works in epochs. Every request admitted so far advances by up to
-`epoch_sweeps` sweeps in one batched call (`ising_sweep_batch_plan`, the
-stepped plan, which spreads every lattice over the whole GPU; with sides
-that are multiples of 16 each sweep is one pass over the tiles of all
-lattices, every lattice alternating between two buffers). Between
+`epoch_sweeps` sweeps in one batched call (`ising_sweep_batch_plan` with
+the AUTO plan: with lattices above 256 on a side in flight, the stepped
+plan, which spreads every lattice over the whole GPU, one pass per sweep
+over the tiles of all lattices, each alternating between two buffers;
+with only small lattices, one workgroup per lattice). Between
 epochs, requests that have arrived are admitted first come, first served,
 as long as the HBM budget (the sum of the admitted lattices' device bytes)
 and the slot limit allow; requests whose sweeps are done are retired.
@@ -73,7 +74,8 @@ class GpuExecutor:
         self.side = {}                             # context -> side
 
     def _bytes(self, L):
-        # the stepped plan alternates a lattice between two buffers
+        # the stepped plan alternates a lattice between two buffers (the
+        # second is allocated on the first stepped epoch)
         return self.b.ising_state_bytes(L, self.b.ISING_PLAN_FUSED) or 2 * L * L
 
     def bytes_for(self, run):
@@ -93,7 +95,7 @@ class GpuExecutor:
         return handle
 
     def step(self, handles, sweeps):
-        self.b.ising_sweep_batch_plan(handles, sweeps, self.b.ISING_BATCH_STEPPED)
+        self.b.ising_sweep_batch_plan(handles, sweeps, self.b.ISING_BATCH_AUTO)
 
     def prefetch(self, handle):
         """Start reading back a request's results as soon as its last epoch
