@@ -3,11 +3,15 @@
 // every lattice (ising_multi_fused.hip, ising_multi.hip), replayed from
 // captured hipGraphs.
 //
-// Per device the engine owns a device array of lattice descriptors, the
-// queue order and a header, plus pinned host copies used to stage them. A
-// call stages the descriptors (longest work first), copies them with one
-// async copy each, and replays the graph, whose single kernel node reads
-// them; the graph is captured once per buffer generation.
+// Per device the engine owns one staging block (headers, queue order, tile
+// starts and lattice descriptors) on the device with a pinned host mirror,
+// the stepped plans' per-tile partials, and its own launch stream. A call
+// fills the mirror, copies it to the device with one copy kernel on the
+// launch stream, and replays the plan's graph, whose kernels read the
+// block; the graphs are captured once per buffer generation. The launch is
+// ordered after every context's earlier work (an event per context whose
+// stream saw other work since the engine last ordered it) and every
+// context's later work after the launch (one event, waited on per stream).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
