@@ -61,7 +61,7 @@ PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
                   "valu_lane_ops_per_attempt": 192905879841.0 * 64 / (388630784 * 2000),
                   "valu_busy_rocprof": 0.951}
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_MULTI_FUSED_SOURCES = "deba87c1b56f686e"
+PROFILED_MULTI_FUSED_SOURCES = "7c1c6aec85944257"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
                         "valu_lane_ops_per_attempt": 123302633.0 * 64 / 388630784,
                         "valu_busy_rocprof": 0.769,

@@ -7,12 +7,14 @@
 // buffer s & 1 of the item (p = the current lattice, q = the other one) and
 // writes the other. A wave walks one tile of up to 32 rows (8 or 16 when a
 // call has too few tiles to fill the GPU) by 128 words of a plane row (two
-// words per lane), exactly as the single-lattice fused kernel does, with two
-// differences:
+// words per lane), exactly as the single-lattice fused kernel does, with
+// three differences:
 //   - tiles at a lattice's right and bottom edges may be narrower and
 //     shorter: lanes past the lattice's last word shadow its last lane
 //     (their loads stay in range, nothing of theirs is stored or counted),
 //     and that lane takes its right neighbour from the edge word;
+//   - a lattice's last column, when at most 32 lanes wide, packs several of
+//     its row bands into one wave (see mf_tile_packed and mf_layout);
 //   - each tile writes its (B, M) to a partial slot of its own, and the last
 //     node of a replay sums them per lattice into the series (no atomics: a
 //     lattice of thousands of tiles would serialise them on one address).
