@@ -92,7 +92,19 @@ def batched_roofline(res, stepped):
     return roof
 
 
-def kernel_sources_hash(files=("ising_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")):
+HEADLINE_FILES = ("ising_fused.hip", "ising_fused_rows.hip", "ising_fused_core.hpp", "ising_device.hpp",
+                  "ising_launch.hpp")
+
+
+def headline_profile(kname):
+    """The recorded counters of the timed headline kernel, or None when the
+    sources changed since they were taken."""
+    if kernel_sources_hash() != PROFILED_SOURCES:
+        return None
+    return PROFILED.get(kname)
+
+
+def kernel_sources_hash(files=HEADLINE_FILES):
     import hashlib
     h = hashlib.sha256()
     for f in files:
@@ -111,7 +123,7 @@ def host_cores():
         return os.cpu_count() or 1
 
 
-def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None, first=2):
+def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None, first=2, force_plan=5):
     """Returns dict with timing, plan and the series of the first sweeps."""
     ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
     try:
@@ -119,7 +131,7 @@ def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None, fi
         b.ising_sweep(ctx, first)
         _, B0, M0 = b.ising_observables(ctx, b.ISING_OBS_SERIES)
         if force:
-            b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, force[0], force[1])
+            b.ising_plan_set(ctx, force_plan, force[0], force[1])
         elif tune:
             b.ising_tune(ctx, 8)
         plan = b.ising_plan_info(ctx)
@@ -519,8 +531,9 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--cw", type=int, default=0, help="force the fused plan with this chunk width")
-    ap.add_argument("--rows", type=int, default=0, help="force the fused plan with this tile height")
+    ap.add_argument("--cw", type=int, default=0, help="force a fused plan with this chunk width")
+    ap.add_argument("--rows", type=int, default=0, help="force a fused plan with this tile / band height")
+    ap.add_argument("--plan", type=int, default=5, help="fused plan forced by --cw/--rows (2: wave tiles, 5: full rows)")
     ap.add_argument("--no-extra", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=8,
@@ -574,18 +587,18 @@ def main():
     run = W.C2_HEADLINE
     force = (args.cw, args.rows) if (args.cw or args.rows) else None
     head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force,
-                        first=max(2, args.cpu_sweeps))
+                        first=max(2, args.cpu_sweeps), force_plan=args.plan)
     ms, steps = head["ms"], args.steps
     attempts = run.L * run.L * steps
     value = attempts / ms / 1e6  # attempts per ns
     launch_ms = ms / steps      # one fused launch per sweep (plus one tiny reduce per call)
-    plan_names = {1: "two-pass", 2: "fused", 3: "resident", 4: "generic"}
+    plan_names = {1: "two-pass", 2: "fused", 3: "resident", 4: "generic", 5: "fused-rows"}
     plan = head["plan"]
-    alg_bytes = 2.0 * run.L * run.L if plan[0] == 2 else 3.0 * run.L * run.L
+    alg_bytes = 2.0 * run.L * run.L if plan[0] in (2, 5) else 3.0 * run.L * run.L
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
 
-    kname = f"k_fused<{plan[1]},{plan[2]}>" if plan[0] == 2 else "k_two_pass"
-    prof = PROFILED.get(kname) if kernel_sources_hash() == PROFILED_SOURCES else None
+    kname = {2: f"k_fused<{plan[1]},{plan[2]}>", 5: f"k_fused_rows<{plan[1]},{plan[2]}>"}.get(plan[0], "k_two_pass")
+    prof = headline_profile(kname)
     same_kernel = prof is not None
     traffic = prof["hbm_bytes_per_launch"] / (launch_ms * 1e-3) / 1e9 if same_kernel else None
     roof_hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

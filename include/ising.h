@@ -62,14 +62,16 @@ extern "C" {
 #define ISING_MAX_L 65536u     /* counter word 0 holds site/8: L*L/8 must fit 32 bits */
 
 /* Plan selection (ising_params.flags, low byte). AUTO picks per lattice side:
- * the fused one-pass sweep for large sides, the workgroup-resident kernel
- * for small ones, the two-pass in-place sweep otherwise. The others force a
- * path (ISING_EUNSUPPORTED if the side does not fit that path). */
+ * the workgroup-resident kernel for small sides, the fused one-pass sweep by
+ * full-row workgroups where a row fits one workgroup, the fused sweep by
+ * wave tiles for larger sides, the two-pass in-place sweep otherwise. The
+ * others force a path (ISING_EUNSUPPORTED if the side does not fit it). */
 #define ISING_PLAN_AUTO 0u
 #define ISING_PLAN_TWO_PASS 1u  /* one launch per colour, in place */
-#define ISING_PLAN_FUSED 2u     /* one launch per sweep, ping-pong buffers */
+#define ISING_PLAN_FUSED 2u     /* one launch per sweep, ping-pong buffers; a wave per tile */
 #define ISING_PLAN_RESIDENT 3u  /* one workgroup runs all sweeps of the call */
 #define ISING_PLAN_GENERIC 4u   /* per-site draws; the only path for L % 8 != 0 */
+#define ISING_PLAN_FUSED_ROWS 5u /* as FUSED, a workgroup per band of whole rows (L/8 <= 16 * 64 * cw) */
 
 /* Model and run parameters (Section 2.2: L x L lattice, coupling J, field h,
  * temperature T, spin-up probability p_up of the initial state). */
@@ -228,7 +230,8 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
 
 /* Force the plan of a context (ISING_PLAN_*; for ISING_PLAN_FUSED also the
  * chunk width cw in {1, 2, 4} words per lane and the tile height rows in
- * {4, 8, 16, 32, 64}; 0 picks a default). Switching to the fused plan may
+ * {4, 8, 16, 32, 64, 128}; for ISING_PLAN_FUSED_ROWS cw and the band height
+ * rows in {8, 16, 32, 64, 128}, with L/8 / (64 cw) <= 16; 0 picks a default). Switching to the fused plan may
  * allocate a second lattice buffer. Results do not depend on the plan.
  * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);

@@ -69,16 +69,20 @@ __device__ __forceinline__ uint4 philox_p0(uint64_t p0_first, uint32_t c1, uint3
         const uint64_t p0 = r == 0 ? p0_first : (uint64_t)kPhiloxM0 * x0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * x2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), hi1 = (uint32_t)(p1 >> 32);
+        // the round keys are wave-uniform: keep them in scalar registers (the
+        // compiler otherwise copies them into vector registers in long loops)
+        const uint32_t rk0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k0);
+        const uint32_t rk1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)k1);
         uint32_t y0, y2;
         if (r < 2) {  // at least one operand of each XOR is uniform
-            y0 = hi1 ^ x1 ^ k0;
-            y2 = hi0 ^ x3 ^ k1;
+            y0 = hi1 ^ x1 ^ rk0;
+            y2 = hi0 ^ x3 ^ rk1;
         } else if (r == 2) {  // x3 is still uniform here
-            y0 = xor3(hi1, x1, k0);
-            y2 = hi0 ^ x3 ^ k1;
+            y0 = xor3(hi1, x1, rk0);
+            y2 = hi0 ^ x3 ^ rk1;
         } else {
-            y0 = xor3(hi1, x1, k0);
-            y2 = xor3(hi0, x3, k1);
+            y0 = xor3(hi1, x1, rk0);
+            y2 = xor3(hi0, x3, rk1);
         }
         x1 = (uint32_t)p1;
         x3 = (uint32_t)p0;
@@ -88,6 +92,23 @@ __device__ __forceinline__ uint4 philox_p0(uint64_t p0_first, uint32_t c1, uint3
         k1 += kPhiloxW1;
     }
     return make_uint4(x0, x1, x2, x3);
+}
+
+// m * x + a (64-bit) in one v_mad_u64_u32: x and m in vector registers, a
+// wave-uniform (scalar registers). Written out because the compiler would
+// otherwise merge M0 * x + M0 * r into M0 * (x + r) with a 64-bit sum, a
+// 64 x 32-bit product of three instructions and a move.
+__device__ __forceinline__ uint64_t mad_u64_uniform(uint32_t x, uint32_t m, uint64_t a) {
+    uint64_t d, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(carry) : "v"(x), "v"(m), "s"(a));
+    return d;
+}
+
+// m * x (64-bit) in one v_mad_u64_u32, for the same reason.
+__device__ __forceinline__ uint64_t mul_u64(uint32_t x, uint32_t m) {
+    uint64_t d, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(d), "=s"(carry) : "v"(x), "v"(m));
+    return d;
 }
 
 // Philox4x32-10 of counter (q, c1, c2, c3) and key (k0, k1).
@@ -106,17 +127,30 @@ struct AcceptTable {
     uint32_t thr_hi[16];
 };
 
-// LDS copy of the table. t32 is read at byte offset 4*code, t64 at 8*code.
+// LDS copy of the table. t32 is read at byte offset 4*code, t64 and tm at
+// 8*code. tm[code] = (2^32 - thr mod 2^32, X): for a draw u, the high word
+// of u + (X 2^32 + lo) is X + [u >= thr] when thr >= 1 and X when thr = 0.
+// X = 1 - s for thr >= 1 and X = s for thr = 0, so bit 0 of that high word
+// is the site's new spin bit in every case (thr = 2^32: lo = 0, a certain
+// flip; thr = 0: lo = 0, never a flip).
 struct LdsTable {
     uint32_t t32[16];
     uint2 t64[16];
+    uint2 tm[16];
 };
+
+__device__ __forceinline__ uint2 mad_entry(uint32_t code, uint32_t thr_lo, uint32_t thr_hi) {
+    const uint32_t s = code >> 3;
+    const bool never = thr_lo == 0u && thr_hi == 0u;
+    return make_uint2(0u - thr_lo, never ? s : 1u - s);
+}
 
 __device__ __forceinline__ void load_table(LdsTable& lt, const AcceptTable& at) {
     const uint32_t tid = threadIdx.x;
     if (tid < 16) {
         lt.t32[tid] = at.thr_m1[tid];
         lt.t64[tid] = make_uint2(at.thr_lo[tid], at.thr_hi[tid]);
+        lt.tm[tid] = mad_entry(tid, at.thr_lo[tid], at.thr_hi[tid]);
     }
 }
 
@@ -155,6 +189,43 @@ __device__ __forceinline__ uint32_t flip_mask_code(const LdsTable& lt, uint32_t 
         const uint32_t f3 = lt64(r.w, a3) ? 0x01000000u : 0u;
         return (f0 | f1) | (f2 | f3);
     }
+}
+
+// 8 * (byte 0 of c) in one op: a shift that reads byte 0 of its operand.
+__device__ __forceinline__ uint32_t byte0_x8(uint32_t c) {
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, 3, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r)
+        : "v"(c));
+    return r;
+}
+
+// High word of u + e (u a 32-bit draw, e a 64-bit table entry) in one
+// v_mad_u64_u32 (u times the inline constant 1, plus e). Written out because
+// the compiler otherwise forms the sum with two or more instructions.
+__device__ __forceinline__ uint32_t mad_hi(uint32_t u, uint64_t e) {
+    uint64_t d, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, 1, %3" : "=v"(d), "=s"(carry) : "v"(u), "v"(e));
+    return (uint32_t)(d >> 32);
+}
+
+// New spins of one word of four sites. code holds 8 s + n per byte (s the
+// spin bit, n the number of up neighbours; at most 12, so bits 5..7 of every
+// byte are 0 and a field of 11 bits starting 3 below a byte is 8 times that
+// byte), r the four draws of the word's Philox call. One LDS read of the
+// site's tm entry and one 64-bit multiply-add give the new spin bit (see
+// LdsTable), for any thresholds in [0, 2^32]; two byte permutes and one
+// three-input logic op assemble the word.
+__device__ __forceinline__ uint32_t accept_word(const LdsTable& lt, uint32_t code, uint4 r) {
+    const uint64_t e0 = lds_at(reinterpret_cast<const uint64_t*>(lt.tm), byte0_x8(code));
+    const uint64_t e1 = lds_at(reinterpret_cast<const uint64_t*>(lt.tm), __builtin_amdgcn_ubfe(code, 5, 11));
+    const uint64_t e2 = lds_at(reinterpret_cast<const uint64_t*>(lt.tm), __builtin_amdgcn_ubfe(code, 13, 11));
+    const uint64_t e3 = lds_at(reinterpret_cast<const uint64_t*>(lt.tm), code >> 21);
+    const uint32_t d0 = mad_hi(r.x, e0), d1 = mad_hi(r.y, e1), d2 = mad_hi(r.z, e2), d3 = mad_hi(r.w, e3);
+    // byte b of the result = byte 0 of d_b (bit 1 of it may be set: masked)
+    const uint32_t w01 = __builtin_amdgcn_perm(d1, d0, 0x0c0c0400u);
+    const uint32_t w23 = __builtin_amdgcn_perm(d3, d2, 0x04000c0cu);
+    return (w01 | w23) & 0x01010101u;
 }
 
 // The same from the spin bits W and the up-neighbour counts n.

@@ -25,6 +25,13 @@ __device__ __forceinline__ uint32_t from_left(uint32_t v, uint32_t edge) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, kDppWaveShr1, 0xf, 0xf, false);
 }
 
+// A compile-time step index for the generic lambdas that stand for the
+// four unrolled steps of a tile walk.
+template <int N>
+struct Step {
+    static constexpr int value = N;
+};
+
 template <int CW>
 struct Row {
     uint32_t v[CW];
@@ -77,8 +84,10 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t rs, uint32_t off, cons
 // Update one lane's CW words of a plane row. P = (i + c) & 1 selects the
 // same-row neighbour side; `edge` is the word just outside the tile on that
 // side (right for P == 1, left for P == 0) of the `same` row. Word w's draw
-// counter is q = (row offset) + xw[w]; m0row = M0 * (row offset), so the
-// first Philox product M0 * q is one multiply-add per word.
+// counter is q = rowoff + xw[w] (rowoff: the row's word offset, wave-uniform
+// unless PACKED; xw[w] = xw[0] + w), so the first Philox product M0 * q is
+// one multiply-add per word: M0 * xw[0] + M0 * (rowoff + w), the second
+// term on the scalar unit.
 //
 // RAGGED: the tile may end before lane 63; `is_last` marks the last lane
 // that holds words of the lattice, whose right neighbour is then `edge`
@@ -86,12 +95,12 @@ __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t rs, uint32_t off, cons
 // bands side by side; `is_first` marks a band's first lane, whose left
 // neighbour is then `edge` rather than the previous lane's word, and `edge`
 // is per lane (its band's).
-template <int CW, bool EXACT, int P, bool OBS, bool RAGGED = false, bool PACKED = false>
+template <int CW, int P, bool OBS, bool RAGGED = false, bool PACKED = false>
 __device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>& own, const Row<CW>& up,
                                               const Row<CW>& dn, const Row<CW>& same, uint32_t edge,
-                                              const Row<CW>& xw, uint64_t m0row, uint32_t t, uint32_t c,
-                                              uint32_t k0, uint32_t k1, uint32_t& sad, bool is_last = false,
-                                              bool is_first = false) {
+                                              const Row<CW>& xw, uint32_t rowoff, uint32_t t, uint32_t c,
+                                              uint32_t k0, uint32_t k1, uint32_t& sad,
+                                              bool is_last = false, bool is_first = false) {
     uint32_t nb = P ? from_right(same.v[0], edge) : from_left(same.v[CW - 1], edge);
     if (RAGGED && P && is_last) nb = edge;
     if (PACKED && !P && is_first) nb = edge;
@@ -106,14 +115,17 @@ __device__ __forceinline__ Row<CW> update_row(const LdsTable& lt, const Row<CW>&
             const uint32_t prv = (w > 0) ? same.v[(w > 0) ? w - 1 : 0] : nb;
             S = __builtin_amdgcn_alignbyte(same.v[w], prv, 3);
         }
-        // table offset 4 (8 s + n), per byte
-        const uint32_t t3 = up.v[w] + dn.v[w] + S;
-        const uint32_t code4 = (((own.v[w] << 3) + t3) + same.v[w]) << 2;
-        const uint32_t n4 = (t3 + same.v[w]) << 2;  // 4 n per byte (colour-1 observables only)
-        const uint4 r = philox_p0((uint64_t)kPhiloxM0 * xw.v[w] + m0row, t, c, 0u, k0, k1);
-        const uint32_t Wn = own.v[w] ^ flip_mask_code<EXACT>(lt, code4, r);
+        const uint32_t n = (up.v[w] + dn.v[w] + S) + same.v[w];  // up neighbours per byte
+        const uint32_t code = (own.v[w] << 3) + n;                 // 8 s + n per byte
+        uint64_t p0;
+        if (PACKED)  // rows differ between the wave's bands: q per lane
+            p0 = mul_u64(rowoff + xw.v[w], kPhiloxM0);
+        else  // xw[w] = xw[0] + w: the word's offset joins the uniform part
+            p0 = mad_u64_uniform(xw.v[0], kPhiloxM0, (uint64_t)kPhiloxM0 * (rowoff + (uint32_t)w));
+        const uint4 r = philox_p0(p0, t, c, 0u, k0, k1);
+        const uint32_t Wn = accept_word(lt, code, r);
         out.v[w] = Wn;
-        if (OBS) sad = sad_misaligned4(Wn, n4, sad);
+        if (OBS) sad = sad_misaligned(Wn, n, sad);
     }
     return out;
 }

@@ -36,10 +36,11 @@ struct PartialReduce {
     int64_t* dst;
 };
 
-// Sum n partial (B, M) pairs into dst (one block; every thread must call).
+// Sum n partial (B, M) pairs into dst (one block of up to 1024 threads;
+// every thread must call).
 __device__ __forceinline__ void reduce_partials(const PartialReduce& red) {
     if (red.n == 0) return;
-    __shared__ int64_t acc[2][4];
+    __shared__ int64_t acc[2][16];
     int64_t b = 0, m = 0;
     uint32_t k = threadIdx.x;
     for (; k + 3 * blockDim.x < red.n; k += 4 * blockDim.x) {  // four loads in flight
@@ -89,6 +90,13 @@ uint32_t fused_tiles(uint32_t L, uint32_t cw, uint32_t rows);
 hipError_t launch_fused(const FusedArgs& a, const AcceptTable& at, bool exact, uint32_t cw, uint32_t rows,
                         const PartialReduce& red, hipStream_t s);
 hipError_t launch_reduce_partials(const PartialReduce& red, hipStream_t s);
+// The fused sweep by full-row workgroups (ising_fused_rows.hip): one
+// workgroup of L/8 / (64 cw) <= 16 waves per band of `rows` rows; a.n_tx is
+// unused and a.part holds one (B, M) pair per band.
+bool fused_rows_supported(uint32_t L, uint32_t cw, uint32_t rows);
+uint32_t fused_rows_bands(uint32_t L, uint32_t rows);
+hipError_t launch_fused_rows(const FusedArgs& a, const AcceptTable& at, uint32_t cw, uint32_t rows,
+                             const PartialReduce& red, hipStream_t s);
 
 // One lattice of a workgroup-resident batch (ising_batch.hip).
 struct BatchItem {

@@ -40,7 +40,6 @@ __device__ __forceinline__ uint32_t wrap_row_m(int i, uint32_t L) {
 }
 
 // Partial (B, M) of one tile of item `it` for its sweep `s` of this call.
-template <bool EXACT>
 __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it, uint32_t tx, uint32_t ty,
                                         uint32_t rows, uint32_t s, int64_t& b_out, int64_t& m_out) {
     constexpr int CW = kMfCW;
@@ -89,7 +88,7 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
         const uint32_t S = pe ? __builtin_amdgcn_alignbyte(nbw, same, 1) : __builtin_amdgcn_alignbyte(same, nbw, 3);
         const uint32_t n = up + dn + same + S;
         const uint4 r = philox(ri * Hw + xe, t, 0u, 0u, k0, k1);
-        edge_c0 = own ^ flip_mask<EXACT>(lt, own, n, r);
+        edge_c0 = accept_word(lt, (own << 3) + n, r);
     }
 
     uint32_t sad = 0, ups = 0, ups8 = 0, dummy = 0;
@@ -101,7 +100,6 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
     const __amdgpu_buffer_rsrc_t rd0 = plane_rsrc(d0), rd1 = plane_rsrc(d1);
     auto rword = [&](int i) { return wrap_row_m(i, L) * Hw; };
     auto rbyte = [&](int i) { return rword(i) * 4u; };
-    auto m0row = [&](int i) { return (uint64_t)kPhiloxM0 * rword(i); };
     Row<CW> c1[4], c0o[2], c0n[4];
     const Row<CW> c1m2 = ld<CW>(rs1, xb, rbyte(r0 - 2));
     const Row<CW> c1m1 = ld<CW>(rs1, xb, rbyte(r0 - 1));
@@ -113,9 +111,9 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
     c0o[1] = ld<CW>(rs0, xb, rbyte(r0 + 1));
     const uint32_t eR = row_ptr(s1, r0 - 1)[xr];
     const uint32_t eL = row_ptr(s1, r0)[xl];
-    c0n[0] = update_row<CW, EXACT, 1, false, true>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, m0row(r0 - 1), t, 0u, k0,
+    c0n[0] = update_row<CW, 1, false, true>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, rword(r0 - 1), t, 0u, k0,
                                                    k1, dummy, is_last);
-    c0n[1] = update_row<CW, EXACT, 0, false, true>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, m0row(r0), t, 0u, k0,
+    c0n[1] = update_row<CW, 0, false, true>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, rword(r0), t, 0u, k0,
                                                    k1, dummy, is_last);
     if (active) st<CW>(rd0, xb + rbyte(r0), c0n[1]);
 
@@ -128,20 +126,20 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
             c0o[u & 1] = ld<CW>(rs0, xb, rbyte(i + 2));
             const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c1, k + u);
             const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)edge_c0, k + u);
-            const uint64_t m1 = m0row(i + 1);
-            const uint64_t m0 = m0row(i);
+            const uint32_t m1 = rword(i + 1);
+            const uint32_t m0 = rword(i);
             Row<CW> c1n;
             if ((u & 1) == 0) {
                 c0n[(u + 2) & 3] =
-                    update_row<CW, EXACT, 1, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                    update_row<CW, 1, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
                                                           c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy, is_last);
-                c1n = update_row<CW, EXACT, 1, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                c1n = update_row<CW, 1, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
                                                            c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad, is_last);
             } else {
                 c0n[(u + 2) & 3] =
-                    update_row<CW, EXACT, 0, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
+                    update_row<CW, 0, false, true>(lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3],
                                                           c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1, dummy, is_last);
-                c1n = update_row<CW, EXACT, 0, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                c1n = update_row<CW, 0, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
                                                            c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad, is_last);
             }
             if (active) {
@@ -157,9 +155,9 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
     }
 
     // partials of the lanes that hold lattice words: B = 16 * words - 2 *
-    // (sad / 4), M = 2 * ups - 8 * words
+    // sad, M = 2 * ups - 8 * words
     const int64_t words = active ? (int64_t)R * CW : 0;
-    int64_t b = active ? 16 * words - (int64_t)(sad >> 1) : 0;
+    int64_t b = active ? 16 * words - 2 * (int64_t)sad : 0;
     int64_t m = active ? 2 * (int64_t)ups - 8 * words : 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -179,7 +177,6 @@ __device__ __forceinline__ void mf_tile(const LdsTable& lt, const BatchItem& it,
 // in step; each lane addresses its band's rows through its own offsets. The
 // edge words of band b's rows are computed by lanes b rows .. b rows +
 // rows - 1 and fetched with a lane permute.
-template <bool EXACT>
 __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchItem& it, uint32_t tx, uint32_t ty0,
                                                uint32_t bands, uint32_t rows, uint32_t s, int64_t& b_out,
                                                int64_t& m_out) {
@@ -232,7 +229,7 @@ __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchIt
         const uint32_t S4 = pe ? __builtin_amdgcn_alignbyte(nbw, same, 1) : __builtin_amdgcn_alignbyte(same, nbw, 3);
         const uint32_t n = up + dn + same + S4;
         const uint4 r = philox(ri * Hw + xe, t, 0u, 0u, k0, k1);
-        edge_c0 = own ^ flip_mask<EXACT>(lt, own, n, r);
+        edge_c0 = accept_word(lt, (own << 3) + n, r);
     }
 
     uint32_t sad = 0, ups = 0, ups8 = 0, dummy = 0;
@@ -244,7 +241,7 @@ __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchIt
     const __amdgpu_buffer_rsrc_t rd0 = plane_rsrc(d0), rd1 = plane_rsrc(d1);
     // byte offset of this lane's word in row rb + d, and the Philox row term
     auto vrow = [&](int d) { return xb + wrap_row_m(rb + d, L) * Hw * 4u; };
-    auto m0of = [&](uint32_t vo) { return (uint64_t)kPhiloxM0 * ((vo - xb) >> 2); };
+    auto m0of = [&](uint32_t vo) { return (vo - xb) >> 2; };  // row word offset of this lane's band
     Row<CW> c1[4], c0o[2], c0n[4];
     uint32_t vo[4];  // offsets of rows i .. i + 3 (ring, slot (i - rb) & 3)
     const uint32_t vm2 = vrow(-2), vm1 = vrow(-1);
@@ -261,9 +258,9 @@ __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchIt
     c0o[1] = ld<CW>(rs0, vo[1], 0u);
     const uint32_t eR = row_ptr(s1, rb - 1)[xr];
     const uint32_t eL = row_ptr(s1, rb)[xl];
-    c0n[0] = update_row<CW, EXACT, 1, false, true, true>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, m0of(vm1), t, 0u, k0,
+    c0n[0] = update_row<CW, 1, false, true, true>(lt, c0om1, c1m2, c1[0], c1m1, eR, xw, m0of(vm1), t, 0u, k0,
                                                          k1, dummy, is_last, is_first);
-    c0n[1] = update_row<CW, EXACT, 0, false, true, true>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, m0of(vo[0]), t, 0u,
+    c0n[1] = update_row<CW, 0, false, true, true>(lt, c0o[0], c1m1, c1[1], c1[0], eL, xw, m0of(vo[0]), t, 0u,
                                                          k0, k1, dummy, is_last, is_first);
     if (active) st<CW>(rd0, vo[0], c0n[1]);
 
@@ -278,21 +275,21 @@ __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchIt
             c0o[u & 1] = ld<CW>(rs0, vo[(u + 2) & 3], 0u);
             const uint32_t e1 = (uint32_t)__builtin_amdgcn_ds_bpermute(eb0 + 4 * i, (int)edge_c1);
             const uint32_t e0 = (uint32_t)__builtin_amdgcn_ds_bpermute(eb0 + 4 * i, (int)edge_c0);
-            const uint64_t m1 = m0of(vo[(u + 1) & 3]);
-            const uint64_t m0 = m0of(vo[u & 3]);
+            const uint32_t m1 = m0of(vo[(u + 1) & 3]);
+            const uint32_t m0 = m0of(vo[u & 3]);
             Row<CW> c1n;
             if ((u & 1) == 0) {
-                c0n[(u + 2) & 3] = update_row<CW, EXACT, 1, false, true, true>(
+                c0n[(u + 2) & 3] = update_row<CW, 1, false, true, true>(
                     lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3], c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1,
                     dummy, is_last, is_first);
-                c1n = update_row<CW, EXACT, 1, true, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                c1n = update_row<CW, 1, true, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
                                                                  c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad,
                                                                  is_last, is_first);
             } else {
-                c0n[(u + 2) & 3] = update_row<CW, EXACT, 0, false, true, true>(
+                c0n[(u + 2) & 3] = update_row<CW, 0, false, true, true>(
                     lt, c0o[(u + 1) & 1], c1[u & 3], c1[(u + 2) & 3], c1[(u + 1) & 3], e1, xw, m1, t, 0u, k0, k1,
                     dummy, is_last, is_first);
-                c1n = update_row<CW, EXACT, 0, true, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
+                c1n = update_row<CW, 0, true, true, true>(lt, c1[u & 3], c0n[u & 3], c0n[(u + 2) & 3],
                                                                  c0n[(u + 1) & 3], e0, xw, m0, t, 1u, k0, k1, sad,
                                                                  is_last, is_first);
             }
@@ -309,7 +306,7 @@ __device__ __forceinline__ void mf_tile_packed(const LdsTable& lt, const BatchIt
     }
 
     const int64_t words = active ? (int64_t)R * CW : 0;
-    int64_t b = active ? 16 * words - (int64_t)(sad >> 1) : 0;
+    int64_t b = active ? 16 * words - 2 * (int64_t)sad : 0;
     int64_t m = active ? 2 * (int64_t)ups - 8 * words : 0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -345,10 +342,7 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
         const BatchItem& it = items[lo];
         if (sweep >= it.n) continue;  // this lattice is done: the whole wave skips
         // this wave's copy of the item's acceptance table
-        if (lane < 16) {
-            lt[wv].t32[lane] = it.table.thr_m1[lane];
-            lt[wv].t64[lane] = make_uint2(it.table.thr_lo[lane], it.table.thr_hi[lane]);
-        }
+        if (lane < 16) lt[wv].tm[lane] = mad_entry(lane, it.table.thr_lo[lane], it.table.thr_hi[lane]);
         __builtin_amdgcn_wave_barrier();
         const MfLayout lay = mf_layout(it.L, rows);
         const uint32_t tile = g - tile_start[lo];
@@ -357,13 +351,11 @@ __global__ void __launch_bounds__(kMfThreads) k_multi_fused(const BatchItem* __r
         if (lay.pack > 1u && tile >= full) {
             const uint32_t ty0 = (tile - full) * lay.pack;
             const uint32_t bands = min(lay.pack, lay.n_typ - ty0);
-            if (it.exact) mf_tile_packed<true>(lt[wv], it, lay.n_tx - 1u, ty0, bands, lay.prow, sweep, b, m);
-            else mf_tile_packed<false>(lt[wv], it, lay.n_tx - 1u, ty0, bands, lay.prow, sweep, b, m);
+            mf_tile_packed(lt[wv], it, lay.n_tx - 1u, ty0, bands, lay.prow, sweep, b, m);
         } else {
             const uint32_t cols = lay.pack > 1u ? lay.n_tx - 1u : lay.n_tx;
             const uint32_t tx = tile % cols, ty = tile / cols;
-            if (it.exact) mf_tile<true>(lt[wv], it, tx, ty, rows, sweep, b, m);
-            else mf_tile<false>(lt[wv], it, tx, ty, rows, sweep, b, m);
+            mf_tile(lt[wv], it, tx, ty, rows, sweep, b, m);
         }
         if (lane == 0) {
             part[2ull * g] = b;

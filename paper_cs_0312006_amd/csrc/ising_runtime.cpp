@@ -66,7 +66,7 @@ static bool valid_params(const ising_params* p) {
     if (p->L < 2 || (p->L & 1u) || p->L > ISING_MAX_L) return false;
     if (!std::isfinite(p->J) || !std::isfinite(p->h) || !std::isfinite(p->T) || !(p->T > 0.0)) return false;
     if (!(p->p_up >= 0.0 && p->p_up <= 1.0)) return false;
-    if ((p->flags & 0xffu) > ISING_PLAN_GENERIC) return false;
+    if ((p->flags & 0xffu) > ISING_PLAN_FUSED_ROWS) return false;
     return true;
 }
 
@@ -105,6 +105,37 @@ constexpr uint32_t kFusedMinTiles = 16384;
 // by more than this fraction (timing noise must not flip the choice).
 constexpr float kTuneMargin = 0.03f;
 constexpr uint32_t kTuneRounds = 3;
+
+// Full-row fused shape: the widest chunk whose workgroup spans the row in at
+// most 16 waves, with the tallest band that still gives 4096 waves (four per
+// SIMD on 256 compute units: at 32768^2, 128-row bands, one workgroup per
+// compute unit), else the shape with the most waves.
+static bool default_fused_rows(uint32_t L, uint32_t* cw_out, uint32_t* rows_out) {
+    static const uint32_t cws[3] = {4, 2, 1};
+    static const uint32_t rs[5] = {128, 64, 32, 16, 8};
+    uint64_t best = 0;
+    uint32_t bcw = 0, br = 0;
+    for (uint32_t cw : cws) {
+        for (uint32_t r : rs) {
+            if (!fused_rows_supported(L, cw, r)) continue;
+            const uint64_t waves = (uint64_t)(L / 8u / (64u * cw)) * fused_rows_bands(L, r);
+            if (waves >= 4096) {
+                *cw_out = cw;
+                *rows_out = r;
+                return true;
+            }
+            if (waves > best) {
+                best = waves;
+                bcw = cw;
+                br = r;
+            }
+        }
+    }
+    if (!best) return false;
+    *cw_out = bcw;
+    *rows_out = br;
+    return true;
+}
 
 static uint32_t default_cw(uint32_t L) {
     const uint32_t Hw = L / 8u;
@@ -167,6 +198,18 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
                 if (!fused_supported(L, pl.cw, pl.rows)) return false;
             }
             break;
+        case ISING_PLAN_FUSED_ROWS:
+            pl.kind = ISING_PLAN_FUSED_ROWS;
+            if (cw == 0 && rows == 0) {
+                if (!default_fused_rows(L, &pl.cw, &pl.rows)) return false;
+            } else {
+                uint32_t dcw = 0, dr = 0;
+                const bool have = default_fused_rows(L, &dcw, &dr);
+                pl.cw = cw ? cw : (have ? dcw : 1);
+                pl.rows = rows ? rows : (have ? dr : 8);
+                if (!fused_rows_supported(L, pl.cw, pl.rows)) return false;
+            }
+            break;
         case ISING_PLAN_AUTO: {
             {
                 std::lock_guard<std::mutex> g(g_tuned_mu);
@@ -178,6 +221,7 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
             }
             if (!words) return plan_for(L, ISING_PLAN_GENERIC, 0, 0, out);
             if (L <= kResidentMaxL) return plan_for(L, ISING_PLAN_RESIDENT, 0, 0, out);
+            if (plan_for(L, ISING_PLAN_FUSED_ROWS, 0, 0, out)) return true;
             if (plan_for(L, ISING_PLAN_FUSED, 0, 0, out)) return true;
             return plan_for(L, ISING_PLAN_TWO_PASS, 0, 0, out);
         }
@@ -261,7 +305,8 @@ int ctx_reserve_series(ising_ctx* ctx, uint64_t more) {
 // ping-pong, partial-sum buffers sized to the plan's tiles or blocks.
 int ctx_prepare_plan(ising_ctx* ctx) {
     const size_t N = (size_t)ctx->L * ctx->L;
-    if (ctx->plan.kind == ISING_PLAN_FUSED && !ctx->buf[1]) {
+    const bool pingpong = ctx->plan.kind == ISING_PLAN_FUSED || ctx->plan.kind == ISING_PLAN_FUSED_ROWS;
+    if (pingpong && !ctx->buf[1]) {
         if (hipMalloc(&ctx->buf[1], N) != hipSuccess) {
             (void)hipGetLastError();
             return ISING_ENOMEM;
@@ -271,6 +316,7 @@ int ctx_prepare_plan(ising_ctx* ctx) {
     uint32_t need = 0;
     const Planes pl = ctx_planes(ctx);
     if (ctx->plan.kind == ISING_PLAN_FUSED) need = fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
+    if (ctx->plan.kind == ISING_PLAN_FUSED_ROWS) need = fused_rows_bands(ctx->L, ctx->plan.rows);
     if (ctx->plan.kind == ISING_PLAN_TWO_PASS) need = two_pass_blocks(pl, ctx->plan.cw);
     if (need > ctx->part_cap) {
         for (int k = 0; k < 2; ++k) {
@@ -291,44 +337,49 @@ int ctx_prepare_plan(ising_ctx* ctx) {
 
 static size_t state_bytes_for(uint32_t L, const Plan& pl) {
     const size_t N = (size_t)L * L;
-    return pl.kind == ISING_PLAN_FUSED ? 2 * N : N;
+    return (pl.kind == ISING_PLAN_FUSED || pl.kind == ISING_PLAN_FUSED_ROWS) ? 2 * N : N;
 }
 
-// n sweeps of the fused plan; series slots ser[0 .. 2n).
-static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser) {
+// n sweeps of either fused plan; series slots ser[0 .. 2n); per-tile (per
+// band) partials alternate between part0 and part1 (each n_tiles pairs).
+static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part0, int64_t* part1) {
+    int64_t* const part[2] = {part0, part1};
     const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
     const uint32_t L = ctx->L, Hw = L / 8u;
     const uint32_t cw = ctx->plan.cw, rows = ctx->plan.rows;
+    const bool by_rows = ctx->plan.kind == ISING_PLAN_FUSED_ROWS;
     const uint32_t n_tx = Hw / (64u * cw);
-    const uint32_t n_tiles = fused_tiles(L, cw, rows);
+    const uint32_t n_tiles = by_rows ? fused_rows_bands(L, rows) : fused_tiles(L, cw, rows);
     for (uint64_t k = 0; k < n; ++k) {
         const uint32_t t = (uint32_t)(ctx->t + k);
         const Planes src = ctx_planes(ctx), dst = ctx_planes_alt(ctx);
         FusedArgs a{reinterpret_cast<const uint32_t*>(src.p[0]), reinterpret_cast<const uint32_t*>(src.p[1]),
                     reinterpret_cast<uint32_t*>(dst.p[0]), reinterpret_cast<uint32_t*>(dst.p[1]),
-                    L, Hw, t, k0, k1, n_tx, n_tiles, ctx->part[k & 1]};
+                    L, Hw, t, k0, k1, n_tx, n_tiles, part[k & 1]};
         PartialReduce red{nullptr, 0, nullptr};
-        if (k > 0) red = PartialReduce{ctx->part[(k - 1) & 1], n_tiles, ser + 2 * (k - 1)};
-        HIP_TRY(ctx, launch_fused(a, ctx->table, ctx->exact, cw, rows, red, ctx->stream));
+        if (k > 0) red = PartialReduce{part[(k - 1) & 1], n_tiles, ser + 2 * (k - 1)};
+        if (by_rows)
+            HIP_TRY(ctx, launch_fused_rows(a, ctx->table, cw, rows, red, ctx->stream));
+        else
+            HIP_TRY(ctx, launch_fused(a, ctx->table, ctx->exact, cw, rows, red, ctx->stream));
         ctx->cur ^= 1;
     }
-    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->part[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)},
-                                        ctx->stream));
+    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{part[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)}, ctx->stream));
     return ISING_OK;
 }
 
-static int sweep_two_pass(ising_ctx* ctx, uint64_t n, int64_t* ser) {
+// n sweeps of the two-pass plan; per-block partials in part (nb pairs).
+static int sweep_two_pass(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part) {
     const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
     const Planes pl = ctx_planes(ctx);
     const uint32_t nb = two_pass_blocks(pl, ctx->plan.cw);
     for (uint64_t k = 0; k < n; ++k) {
         const uint32_t t = (uint32_t)(ctx->t + k);
         PartialReduce red{nullptr, 0, nullptr};
-        if (k > 0) red = PartialReduce{ctx->part[0], nb, ser + 2 * (k - 1)};
-        HIP_TRY(ctx, launch_two_pass(pl, ctx->table, ctx->exact, ctx->plan.cw, t, k0, k1, ctx->part[0], red,
-                                     ctx->stream));
+        if (k > 0) red = PartialReduce{part, nb, ser + 2 * (k - 1)};
+        HIP_TRY(ctx, launch_two_pass(pl, ctx->table, ctx->exact, ctx->plan.cw, t, k0, k1, part, red, ctx->stream));
     }
-    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{ctx->part[0], nb, ser + 2 * (n - 1)}, ctx->stream));
+    HIP_TRY(ctx, launch_reduce_partials(PartialReduce{part, nb, ser + 2 * (n - 1)}, ctx->stream));
     return ISING_OK;
 }
 
@@ -486,8 +537,9 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
     }
     int64_t* ser = ctx->series + 2 * ctx->series_len;
     switch (ctx->plan.kind) {
-        case ISING_PLAN_FUSED: rc = sweep_fused(ctx, n, ser); break;
-        case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser); break;
+        case ISING_PLAN_FUSED:
+        case ISING_PLAN_FUSED_ROWS: rc = sweep_fused(ctx, n, ser, ctx->part[0], ctx->part[1]); break;
+        case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser, ctx->part[0]); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, ser); break;
         default: return ISING_EUNSUPPORTED;
     }
@@ -782,7 +834,7 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;
-    if (plan == ISING_PLAN_AUTO || plan > ISING_PLAN_GENERIC) return ISING_EINVAL;
+    if (plan == ISING_PLAN_AUTO || plan > ISING_PLAN_FUSED_ROWS) return ISING_EINVAL;
     Plan pl;
     if (!plan_for(ctx->L, plan, cw, rows, &pl)) return ISING_EUNSUPPORTED;
     const Plan old = ctx->plan;
@@ -804,10 +856,13 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
         cands.push_back(pl);
     } else {
         static const uint32_t cws[3] = {1, 2, 4};
-        static const uint32_t rs[5] = {4, 8, 16, 32, 64};
+        static const uint32_t rs[6] = {4, 8, 16, 32, 64, 128};
         for (uint32_t cw : cws)
             for (uint32_t r : rs)
                 if (plan_for(L, ISING_PLAN_FUSED, cw, r, &pl)) cands.push_back(pl);
+        for (uint32_t cw : cws)
+            for (uint32_t r : rs)
+                if (r >= 8 && plan_for(L, ISING_PLAN_FUSED_ROWS, cw, r, &pl)) cands.push_back(pl);
         for (uint32_t cw : cws)
             if (plan_for(L, ISING_PLAN_TWO_PASS, cw, 0, &pl)) cands.push_back(pl);
         if (L <= 1024 && plan_for(L, ISING_PLAN_RESIDENT, 0, 0, &pl)) cands.push_back(pl);
@@ -825,9 +880,11 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
     bool have = false;
     // the default plan for this side is timed first and kept unless beaten
     Plan dflt;
-    if (plan_for(L, L % 8u ? ISING_PLAN_GENERIC : (L <= kResidentMaxL ? ISING_PLAN_RESIDENT : ISING_PLAN_FUSED),
-                 0, 0, &dflt) ||
-        plan_for(L, ISING_PLAN_TWO_PASS, 0, 0, &dflt)) {
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        g_tuned.erase(L);  // the default is the untuned AUTO choice
+    }
+    if (plan_for(L, ISING_PLAN_AUTO, 0, 0, &dflt)) {
         for (size_t k = 0; k < cands.size(); ++k) {
             if (cands[k].kind == dflt.kind && cands[k].cw == dflt.cw && cands[k].rows == dflt.rows) {
                 std::swap(cands[0], cands[k]);

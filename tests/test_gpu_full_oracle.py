@@ -73,16 +73,17 @@ def test_c1_4096_all_2000_sweeps(b, o, k):
 
 
 C2_SWEEPS = 8
-C2_SHAPES = [(4, 8), (4, 16), (4, 32), (4, 64), (2, 32)]
+C2_SHAPES = [("FUSED", 4, 16), ("FUSED", 4, 32), ("FUSED", 4, 64), ("FUSED", 4, 128), ("FUSED", 2, 32),
+             ("FUSED_ROWS", 4, 32), ("FUSED_ROWS", 4, 64), ("FUSED_ROWS", 4, 128)]
 
 
 @pytest.mark.parametrize("k", [0, 1, 2, 3])
 def test_c2_32768_whole_lattice_first_sweeps(b, o, k):
     """32768 x 32768 (1 GiB), h in {0, 0.1} x {cold, hot}, seed 11: after the
     first 8 sweeps the whole lattice, its hash and the 8 (B_t, M_t) equal a
-    full oracle run, for the default plan and each fused tile shape the
-    autotuner picks at this side (the later sweeps are checked through
-    light-cone windows in test_gpu_parity)."""
+    full oracle run, for the default plan and each fused shape (wave tiles
+    and full-row workgroups) the autotuner picks at this side (the later
+    sweeps are checked through light-cone windows in test_gpu_parity)."""
     run = W.C2[k]
     G.log(f"C2 32768 h={run.h} p_up={run.p_up}: oracle {C2_SWEEPS} sweeps")
     ref = G.oracle_run(o, run, sweeps=C2_SWEEPS)
@@ -91,7 +92,7 @@ def test_c2_32768_whole_lattice_first_sweeps(b, o, k):
         ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
         try:
             if shape:
-                b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, shape[0], shape[1])
+                b.ising_plan_set(ctx, getattr(b, "ISING_PLAN_" + shape[0]), shape[1], shape[2])
             b.ising_sweep(ctx, C2_SWEEPS)
             g = _ctx_result(b, ctx, run.L)
             plan = tuple(b.ising_plan_info(ctx))

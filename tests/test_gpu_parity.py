@@ -277,7 +277,7 @@ def _check_windows(o, run, spins, sweeps, corners, W_extra=16):
     return checked
 
 
-FUSED_SHAPES = [(cw, rows) for cw in (1, 2, 4) for rows in (4, 8, 16, 32, 64)]
+FUSED_SHAPES = [(cw, rows) for cw in (1, 2, 4) for rows in (4, 8, 16, 32, 64, 128)]
 
 
 @pytest.mark.parametrize("L", [8192, 16384])

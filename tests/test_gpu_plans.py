@@ -55,6 +55,29 @@ def test_fused_every_tile_shape(b, o, L, h, T):
     assert tried >= 4
 
 
+@pytest.mark.parametrize("L,h,T", [(2048, 0.0, 2.269185), (2048, 0.1, 1.8), (1024, 0.0, 0.2), (512, -0.05, 3.0),
+                                   (4096, 0.0, 1e300), (1536, 0.02, 2.5)])
+def test_fused_rows_every_shape(b, o, L, h, T):
+    """The fused sweep by full-row workgroups (neighbouring waves trade their
+    edge words through local memory) in every chunk width and band height
+    that fits the side, against the oracle; also the zero thresholds of
+    T = 0.2 and the certain flips of T = 1e300."""
+    run = W.Run(L=L, h=h, T=T, seed=L + 5, sweeps=12)
+    ref = G.oracle_run(o, run)
+    tried = 0
+    for cw in (1, 2, 4):
+        for rows in (8, 16, 32, 64, 128):
+            nw = (L // 8) // (64 * cw)
+            if (L // 8) % (64 * cw) or nw > 16 or L % rows:
+                continue
+            G.log(f"fused rows L={L} cw={cw} rows={rows} h={h} T={T}")
+            g = _run_plan(b, run, b.ISING_PLAN_FUSED_ROWS, cw, rows, chunks=[5, 7])
+            assert g["plan"] == (b.ISING_PLAN_FUSED_ROWS, cw, rows)
+            G.assert_same(g, ref, f"fused rows L={L} cw={cw} rows={rows}")
+            tried += 1
+    assert tried >= 3
+
+
 @pytest.mark.parametrize("L", [8, 16, 24, 40, 64, 128, 200, 520])
 def test_resident_plan(b, o, L):
     run = W.Run(L=L, h=0.03, T=2.1, seed=L, sweeps=30)
@@ -75,13 +98,14 @@ def test_two_pass_chunk_widths(b, o, L):
 def test_plan_switches_mid_run(b, o):
     """The lattice and the sweep index carry over between plans (the fused
     plan's ping-pong buffer included)."""
-    run = W.Run(L=1024, h=0.02, T=2.3, seed=99, sweeps=23)
+    run = W.Run(L=1024, h=0.02, T=2.3, seed=99, sweeps=29)
     ref = G.oracle_run(o, run)
     ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
     G.log("plan switches 1024")
     for plan, cw, rows, n in [(b.ISING_PLAN_FUSED, 1, 8, 3), (b.ISING_PLAN_TWO_PASS, 2, 0, 4),
                               (b.ISING_PLAN_FUSED, 2, 16, 5), (b.ISING_PLAN_RESIDENT, 0, 0, 2),
-                              (b.ISING_PLAN_GENERIC, 0, 0, 2), (b.ISING_PLAN_FUSED, 1, 64, 7)]:
+                              (b.ISING_PLAN_GENERIC, 0, 0, 2), (b.ISING_PLAN_FUSED, 1, 64, 7),
+                              (b.ISING_PLAN_FUSED_ROWS, 2, 8, 3), (b.ISING_PLAN_FUSED_ROWS, 1, 128, 3)]:
         b.ising_plan_set(ctx, plan, cw, rows)
         b.ising_sweep(ctx, n)
     obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
@@ -313,7 +337,7 @@ def test_autotune_keeps_lattice_and_picks_a_plan(b, o):
     after = b.ising_copy_spins(ctx, run.L)
     assert np.array_equal(before, after)
     plan = b.ising_plan_info(ctx)
-    assert plan[0] in (b.ISING_PLAN_FUSED, b.ISING_PLAN_TWO_PASS, b.ISING_PLAN_RESIDENT)
+    assert plan[0] in (b.ISING_PLAN_FUSED, b.ISING_PLAN_FUSED_ROWS, b.ISING_PLAN_TWO_PASS, b.ISING_PLAN_RESIDENT)
     b.ising_sweep(ctx, 4)
     obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
     spins = b.ising_copy_spins(ctx, run.L)
@@ -328,11 +352,14 @@ def test_autotune_keeps_lattice_and_picks_a_plan(b, o):
 
 
 def test_c2_plans_agree_at_full_size(b):
-    """32768 x 32768, 40 sweeps: fused and two-pass plans give the same
-    lattice hash and series (plan independence at the full size)."""
+    """32768 x 32768, 40 sweeps: the fused plans (wave tiles and full-row
+    workgroups) and the two-pass plan give the same lattice hash and series
+    (plan independence at the full size)."""
     run = W.Run(L=32768, seed=11, p_up=0.5, sweeps=40)
     G.log("C2 fused vs two-pass 40 sweeps")
     f = _run_plan(b, run, b.ISING_PLAN_FUSED)
     t = _run_plan(b, run, b.ISING_PLAN_TWO_PASS)
-    assert f["hash"] == t["hash"]
+    r = _run_plan(b, run, b.ISING_PLAN_FUSED_ROWS)
+    assert f["hash"] == t["hash"] == r["hash"]
     assert np.array_equal(f["B"], t["B"]) and np.array_equal(f["M"], t["M"])
+    assert np.array_equal(r["B"], t["B"]) and np.array_equal(r["M"], t["M"])
