@@ -140,6 +140,28 @@ int ising_create_in(const ising_params* params, void* dev_buf, size_t bytes, voi
  * ERANGE (t + n > 2^32), ESTATE, ENOMEM (series buffer growth), EDEVICE. */
 int ising_sweep(ising_ctx* ctx, uint64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * n sweeps as ising_sweep, with two differences. The per-sweep pairs
+ * (B_t, M_t) are written to the caller's device array series_dev (2 n
+ * int64: B_t then M_t for each sweep, oldest first) instead of the
+ * context's pending series, which stays as it is. And the sweep kernels'
+ * per-tile (fused plan) or per-block (two-pass plan) partial sums go to a
+ * fixed device array inside the library of ISING_STATIC_SCRATCH_PAIRS int64
+ * pairs (1 MiB; each device that runs this call holds its own copy until the
+ * process ends) instead of context memory. No device memory is allocated or
+ * freed and nothing is synchronised; the work is enqueued on the context's
+ * stream. Every call on one device shares that device's array and leaves
+ * its last contents there (the kernels write each slot before they read
+ * it): calls that overlap on one device, on any streams, race and must be
+ * ordered by the caller. The fused plan needs 2 x its tiles pairs (32768^2
+ * with 32-row tiles: 32768), the two-pass plan one per block; the resident
+ * and per-site plans need none. Errors: EINVAL (NULL ctx or series_dev),
+ * ERANGE (t + n > 2^32, or the plan needs more pairs than the array holds:
+ * pick taller tiles with ising_plan_set), ESTATE, EDEVICE. */
+#define ISING_STATIC_SCRATCH_PAIRS 65536u
+int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev);
+
 /* Synchronise the context's stream and report the current state in *out
  * (may be NULL). With ISING_OBS_HASH the lattice is copied to the host and
  * hashed. With ISING_OBS_SERIES the pending per-sweep series (oldest first)

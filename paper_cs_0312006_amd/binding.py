@@ -22,6 +22,7 @@ ISING_EUNSUPPORTED = -5
 ISING_ESTATE = -6
 
 ISING_MAX_L = 65536
+ISING_STATIC_SCRATCH_PAIRS = 65536
 
 ISING_PLAN_AUTO = 0
 ISING_PLAN_TWO_PASS = 1
@@ -85,6 +86,7 @@ SIGNATURES = {
     "ising_create_in": (C.c_int, [C.POINTER(ising_params), C.c_void_p, C.c_size_t, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "ising_sweep": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "ising_sweep_static": (C.c_int, [C.c_void_p, C.c_uint64, C.c_void_p]),
     "ising_observables": (C.c_int, [C.c_void_p, C.POINTER(ising_obs), C.c_void_p, C.c_void_p, C.c_uint64,
                                     C.c_uint32]),
     "ising_prefetch_observables": (C.c_int, [C.c_void_p, C.c_uint32]),
@@ -200,6 +202,11 @@ def ising_create_in(dev_ptr, nbytes, L, J=1.0, h=0.0, T=2.269185, seed=0, p_up=0
 
 def ising_sweep(ctx, n):
     _check(lib().ising_sweep(ctx, int(n)), "ising_sweep", ctx)
+
+
+def ising_sweep_static(ctx, n, series_dev):
+    """series_dev: device address (int) of 2 n int64."""
+    _check(lib().ising_sweep_static(ctx, int(n), C.c_void_p(int(series_dev))), "ising_sweep_static", ctx)
 
 
 def ising_observables(ctx, want=0, capacity=None):

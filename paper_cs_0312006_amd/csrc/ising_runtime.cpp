@@ -549,6 +549,72 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
     return ISING_OK;
 }
 
+// Device array for ising_sweep_static: the per-tile (or per-block) partial
+// sums of its sweep kernels. One copy per device, for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returned on that device (the array's name is not a device address in host
+// code).
+static __device__ __align__(256) int64_t scratch[2 * ISING_STATIC_SCRATCH_PAIRS];
+static std::mutex g_scratch_mu;
+static int64_t* g_scratch_ptr[64] = {};
+
+// The array's address on `dev` (current), looked up on the first call there.
+static int64_t* static_scratch(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<int64_t*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
+    int rc = ctx_enter(ctx);
+    if (rc != ISING_OK) return rc;
+    if (!series_dev) return ISING_EINVAL;
+    if (n == 0) return ISING_OK;
+    if (ctx->t + n > ((uint64_t)1 << 32)) return ISING_ERANGE;
+    uint32_t pairs = 0;  // partial slots the plan's kernels need
+    if (ctx->plan.kind == ISING_PLAN_FUSED) pairs = 2 * fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
+    if (ctx->plan.kind == ISING_PLAN_FUSED_ROWS) pairs = 2 * fused_rows_bands(ctx->L, ctx->plan.rows);
+    if (ctx->plan.kind == ISING_PLAN_TWO_PASS) pairs = two_pass_blocks(ctx_planes(ctx), ctx->plan.cw);
+    if (pairs > ISING_STATIC_SCRATCH_PAIRS) return ISING_ERANGE;
+    int64_t* sc = nullptr;
+    if (pairs) {
+        sc = static_scratch(ctx->device);
+        if (!sc) return ctx_fail(ctx, hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    }
+    ++ctx->gen;
+    switch (ctx->plan.kind) {
+        case ISING_PLAN_FUSED:
+        case ISING_PLAN_FUSED_ROWS: {
+            const uint32_t tiles = pairs / 2;
+            rc = sweep_fused(ctx, n, series_dev, sc, sc + 2ull * tiles);
+            break;
+        }
+        case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, series_dev, sc); break;
+        case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, series_dev); break;
+        case ISING_PLAN_RESIDENT: {
+            BatchItem it;
+            fill_batch_item(ctx, n, false, it);
+            it.series = series_dev;
+            if (bits_fit(ctx->L) && !bytes_fit(ctx->L)) it.bits = bits_mode(ctx->table);
+            HIP_TRY(ctx, launch_batch_one(it, ctx->stream));
+            rc = ISING_OK;
+            break;
+        }
+        default: return ISING_EUNSUPPORTED;
+    }
+    if (rc != ISING_OK) return rc;
+    ctx->t += n;
+    return ISING_OK;
+}
+
 int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream) {
     return ising_sweep_batch_plan(ctxs, n_sweeps, count, stream, ISING_BATCH_AUTO);
 }
