@@ -146,8 +146,10 @@ __device__ __forceinline__ void update_chunk_inplace(const LdsTable& lt, uint32_
 // (B, M) per block in part[]; colour 0 first folds the previous sweep's
 // partials (if any) into that sweep's series slot.
 template <int CW, bool OBS, bool EXACT>
-__global__ void __launch_bounds__(256) k_two_pass(Planes pl, AcceptTable at, uint32_t c, uint32_t t,
-                                                  uint32_t k0, uint32_t k1, int64_t* part, PartialReduce red) {
+__global__ void __launch_bounds__(256) k_two_pass(Planes pl, AcceptTable at, uint32_t c, uint32_t t_off,
+                                                  uint32_t k0, uint32_t k1, int64_t* part, PartialReduce red,
+                                                  const uint32_t* t_dev) {
+    const uint32_t t = t_dev ? *t_dev + t_off : t_off;  // graph replays read the sweep index from memory
     __shared__ LdsTable lt;
     load_table(lt, at);
     __syncthreads();
@@ -322,23 +324,60 @@ uint32_t two_pass_blocks(const Planes& pl, uint32_t cw) {
 
 template <int CW, bool EXACT>
 static void two_pass_sweep(const Planes& pl, const AcceptTable& at, uint32_t t, uint32_t k0, uint32_t k1,
-                           int64_t* part, const PartialReduce& red, hipStream_t s) {
+                           int64_t* part, const PartialReduce& red, hipStream_t s, const uint32_t* t_dev) {
     const uint32_t nb = two_pass_blocks(pl, CW);
-    k_two_pass<CW, false, EXACT><<<nb, 256, 0, s>>>(pl, at, 0u, t, k0, k1, part, red);
-    k_two_pass<CW, true, EXACT><<<nb, 256, 0, s>>>(pl, at, 1u, t, k0, k1, part, PartialReduce{nullptr, 0, nullptr});
+    k_two_pass<CW, false, EXACT><<<nb, 256, 0, s>>>(pl, at, 0u, t, k0, k1, part, red, t_dev);
+    k_two_pass<CW, true, EXACT><<<nb, 256, 0, s>>>(pl, at, 1u, t, k0, k1, part, PartialReduce{nullptr, 0, nullptr},
+                                                   t_dev);
 }
 
 hipError_t launch_two_pass(const Planes& pl, const AcceptTable& at, bool exact, uint32_t cw, uint32_t t,
-                           uint32_t k0, uint32_t k1, int64_t* part, const PartialReduce& red, hipStream_t s) {
+                           uint32_t k0, uint32_t k1, int64_t* part, const PartialReduce& red, hipStream_t s,
+                           const uint32_t* t_dev) {
     switch (cw * 2 + (exact ? 1 : 0)) {
-        case 2: two_pass_sweep<1, false>(pl, at, t, k0, k1, part, red, s); break;
-        case 3: two_pass_sweep<1, true>(pl, at, t, k0, k1, part, red, s); break;
-        case 4: two_pass_sweep<2, false>(pl, at, t, k0, k1, part, red, s); break;
-        case 5: two_pass_sweep<2, true>(pl, at, t, k0, k1, part, red, s); break;
-        case 8: two_pass_sweep<4, false>(pl, at, t, k0, k1, part, red, s); break;
-        case 9: two_pass_sweep<4, true>(pl, at, t, k0, k1, part, red, s); break;
+        case 2: two_pass_sweep<1, false>(pl, at, t, k0, k1, part, red, s, t_dev); break;
+        case 3: two_pass_sweep<1, true>(pl, at, t, k0, k1, part, red, s, t_dev); break;
+        case 4: two_pass_sweep<2, false>(pl, at, t, k0, k1, part, red, s, t_dev); break;
+        case 5: two_pass_sweep<2, true>(pl, at, t, k0, k1, part, red, s, t_dev); break;
+        case 8: two_pass_sweep<4, false>(pl, at, t, k0, k1, part, red, s, t_dev); break;
+        case 9: two_pass_sweep<4, true>(pl, at, t, k0, k1, part, red, s, t_dev); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// Graph replays of the two-pass plan: the sweep index and series slot of
+// a replay live in a device header the replay's last node advances.
+__global__ void __launch_bounds__(64) k_set_header(SweepHeader* hdr, uint32_t t, int64_t* ser) {
+    if (threadIdx.x == 0) {
+        hdr->t = t;
+        hdr->arrived = 0;
+        hdr->ser = ser;
+    }
+}
+
+// Block k sums sweep k's partials into its series slot. A block has read
+// the header before its thread 0 arrives (the slot's address feeds the
+// store that precedes the arrival), so the last block to arrive may advance
+// the header for the next replay and re-arm the count.
+__global__ void __launch_bounds__(256) k_reduce_group(const int64_t* part, uint32_t n, SweepHeader* hdr) {
+    const uint32_t k = blockIdx.x;
+    reduce_partials(PartialReduce{part + 2ull * k * n, n, hdr->ser + 2ull * k});
+    if (threadIdx.x == 0 && atomicAdd(&hdr->arrived, 1u) == gridDim.x - 1u) {
+        hdr->arrived = 0;
+        hdr->t += gridDim.x;
+        hdr->ser += 2ull * gridDim.x;
+    }
+}
+
+hipError_t launch_set_header(SweepHeader* hdr, uint32_t t, int64_t* ser, hipStream_t s) {
+    k_set_header<<<1, 64, 0, s>>>(hdr, t, ser);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_group(const int64_t* part, uint32_t n, uint32_t g, SweepHeader* hdr, hipStream_t s) {
+    if (n == 0) return hipErrorInvalidValue;  // every block must store, then arrive
+    k_reduce_group<<<g, 256, 0, s>>>(part, n, hdr);
     return hipGetLastError();
 }
 

@@ -29,6 +29,20 @@ struct FusedArgs {
     int64_t* part;     // 2 int64 per tile: partial (B, M)
 };
 
+// Device-side state of a context's graph replays: the sweep index of the
+// replay's first sweep and where its first (B, M) goes. The replay's last
+// node advances both by the replay's sweeps; arrived counts its finished
+// workgroups.
+struct SweepHeader {
+    uint32_t t;
+    uint32_t arrived;
+    int64_t* ser;
+};
+hipError_t launch_set_header(SweepHeader* hdr, uint32_t t, int64_t* ser, hipStream_t s);
+// Sum each of g sweeps' n partial pairs (sweep k's at part + 2 k n) into
+// hdr->ser + 2 k, then advance hdr by g sweeps.
+hipError_t launch_reduce_group(const int64_t* part, uint32_t n, uint32_t g, SweepHeader* hdr, hipStream_t s);
+
 // Sum of n per-tile (or per-block) partial (B, M) pairs into dst[0], dst[1].
 struct PartialReduce {
     const int64_t* part;
@@ -80,7 +94,8 @@ __device__ __forceinline__ void reduce_partials(const PartialReduce& red) {
 hipError_t launch_init(const Planes& pl, bool words, uint32_t k0, uint32_t k1, uint64_t pthr, hipStream_t s);
 uint32_t two_pass_blocks(const Planes& pl, uint32_t cw);
 hipError_t launch_two_pass(const Planes& pl, const AcceptTable& at, bool exact, uint32_t cw, uint32_t t,
-                           uint32_t k0, uint32_t k1, int64_t* part, const PartialReduce& red, hipStream_t s);
+                           uint32_t k0, uint32_t k1, int64_t* part, const PartialReduce& red, hipStream_t s,
+                           const uint32_t* t_dev = nullptr);
 hipError_t launch_generic_sweep(const Planes& pl, const AcceptTable& at, bool exact, uint32_t t, uint32_t k0,
                                 uint32_t k1, int64_t* obs, hipStream_t s);
 hipError_t launch_observe(const Planes& pl, int64_t* out, hipStream_t s);

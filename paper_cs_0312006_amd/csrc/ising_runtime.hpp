@@ -62,6 +62,15 @@ struct ising_ctx {
     int64_t* cpart = nullptr;    // Creutz per-block (B, M) partials
     int64_t* cfpart[2] = {nullptr, nullptr};  // fused Creutz per-tile partials, double-buffered
     uint32_t cfpart_cap = 0;
+    // Graph replays of the two-pass plan (kGraphSweeps sweeps each): the
+    // instantiated graph, the lattice buffer it was captured on, the device
+    // header it reads (sweep index, series slot) and the partials of a
+    // replay's sweeps (kGraphSweeps x blocks pairs).
+    hipGraphExec_t gexec = nullptr;
+    uint32_t gcur = 0;
+    ising::SweepHeader* ghdr = nullptr;
+    int64_t* gpart = nullptr;
+    size_t gpart_pairs = 0;
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;
     hipError_t last_hip = hipSuccess;
@@ -72,6 +81,9 @@ ising::Planes ctx_planes(const ising_ctx* ctx);
 ising::Planes ctx_planes_alt(const ising_ctx* ctx);
 int ctx_reserve_series(ising_ctx* ctx, uint64_t more);
 int ctx_prepare_plan(ising_ctx* ctx);
+// Forget the context's captured sweep graphs (its plan, table or buffers
+// changed); waits for its stream when there are any.
+void ctx_drop_graphs(ising_ctx* ctx);
 // Poison the context after a failed HIP call `where` and return EDEVICE.
 int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 

@@ -114,6 +114,34 @@ def test_plan_switches_mid_run(b, o):
     G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref, "plan switches")
 
 
+def test_two_pass_graph_replays_follow_the_lattice(b, o):
+    """Two-pass calls of 16 or more sweeps run as graph replays (16 sweeps
+    each, the rest launched directly). Between them the lattice moves to the
+    other buffer (a fused sweep, a batch call with an odd sweep count): each
+    later replay still updates the lattice in place, continues the sweep
+    index and fills the next series slots."""
+    run = W.Run(L=512, h=0.05, T=2.1, seed=2024, sweeps=37 + 3 + 16 + 3 + 33 + 15)
+    ref = G.oracle_run(o, run)
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    try:
+        G.log("two-pass graph replays 512")
+        b.ising_plan_set(ctx, b.ISING_PLAN_TWO_PASS, 4, 0)
+        b.ising_sweep(ctx, 37)
+        b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, 1, 8)
+        b.ising_sweep(ctx, 3)
+        b.ising_plan_set(ctx, b.ISING_PLAN_TWO_PASS, 2, 0)
+        b.ising_sweep(ctx, 16)
+        b.ising_sweep_batch_plan([ctx], [3], b.ISING_BATCH_STEPPED)
+        b.ising_sweep(ctx, 33)
+        b.ising_sweep(ctx, 15)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        spins = b.ising_copy_spins(ctx, run.L)
+    finally:
+        b.ising_destroy(ctx)
+    assert obs.sweeps_done == run.sweeps
+    G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, ref, "two-pass graph replays")
+
+
 @pytest.mark.parametrize("plan", ["RESIDENT", "STEPPED"])
 def test_batch_equals_solo_and_oracle(b, o, plan):
     """Uneven lattices (sizes, temperatures, fields, seeds, sweep counts,
