@@ -18,6 +18,13 @@ Because the draws are keyed by (seed, sweep, colour, site), a request's
 result does not depend on which epochs or which other requests it shared
 the GPU with.
 
+The HBM budget covers every context the executor holds on the device: the
+admitted requests' and the idle ones it keeps for reuse. An admission that
+would not fit first reuses an idle context of its side (no new bytes) and
+otherwise frees idle contexts of other sides, oldest retired first, while
+that makes room (freeing synchronises the device, so it happens only when
+the budget requires it).
+
 Up to `depth` epochs are enqueued before the oldest one is waited for:
 which requests take part and how many sweeps each runs is known in
 advance, and every request has its own stream. A request's results are
@@ -58,9 +65,11 @@ class GpuExecutor:
     `pool_bytes`, and re-initialised for later requests of the same side
     (ising_reset) instead of being freed and allocated again: freeing device
     memory synchronises the device, which would drain the epochs queued
-    behind it. Every context's series is reserved at admission for at least
-    `series_floor` sweeps (and the whole request), so neither an epoch nor a
-    reuse grows it. close() releases the kept contexts."""
+    behind it. The server counts the kept bytes against its HBM budget
+    (pooled_bytes, reusable) and has them freed when an admission needs the
+    room (evict). Every context's series is reserved at admission for at
+    least `series_floor` sweeps (and the whole request), so neither an epoch
+    nor a reuse grows it. close() releases the kept contexts."""
 
     def __init__(self, hash_results=True, pool_bytes=8 << 30, series_floor=32768):
         from . import binding as b
@@ -71,6 +80,7 @@ class GpuExecutor:
         self.pooled = 0                   # device bytes of the idle contexts now kept
         self.series_floor = series_floor  # every context's series holds at least this many sweeps
         self.pool = collections.defaultdict(list)  # side -> idle contexts
+        self.order = collections.deque()           # idle contexts, oldest retired first
         self.side = {}                             # context -> side
 
     def _bytes(self, L):
@@ -81,11 +91,37 @@ class GpuExecutor:
     def bytes_for(self, run):
         return self._bytes(run.L)
 
+    def pooled_bytes(self):
+        return self.pooled
+
+    def reusable(self, run):
+        """Whether create(run) takes an idle context (no new device bytes)."""
+        return bool(self.pool.get(run.L))
+
+    def evict(self, nbytes, keep_side=None):
+        """Free idle contexts (not of side keep_side), oldest retired first,
+        until `nbytes` are freed or none is left; returns the bytes freed."""
+        freed = 0
+        for handle in list(self.order):
+            if freed >= nbytes:
+                break
+            L = self.side[handle]
+            if L == keep_side:
+                continue
+            self.order.remove(handle)
+            self.pool[L].remove(handle)
+            del self.side[handle]
+            self.b.ising_destroy(handle)
+            self.pooled -= self._bytes(L)
+            freed += self._bytes(L)
+        return freed
+
     def create(self, run):
         b = self.b
         idle = self.pool.get(run.L)
         if idle:
             handle = idle.pop()
+            self.order.remove(handle)
             self.pooled -= self._bytes(run.L)
             b.ising_reset(handle, run.L, run.J, run.h, run.T, run.seed, run.p_up, b.ISING_PLAN_TWO_PASS)
         else:
@@ -118,6 +154,7 @@ class GpuExecutor:
         need = self._bytes(L)
         if self.pooled + need <= self.pool_bytes:
             self.pool[L].append(handle)
+            self.order.append(handle)
             self.pooled += need
         else:
             del self.side[handle]
@@ -129,10 +166,11 @@ class GpuExecutor:
                 self.b.ising_destroy(handle)
                 del self.side[handle]
         self.pool.clear()
+        self.order.clear()
         self.pooled = 0
 
 
-def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=128,
+def serve(requests, executor, hbm_budget=16 << 30, max_slots=4096, epoch_sweeps=128,
           clock=time.perf_counter, sleep=time.sleep, depth=2):
     """Run a stream of workloads.Request through the executor. Returns
     (results sorted by request id, stats). Up to `depth` epochs are enqueued
@@ -148,6 +186,10 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=1
     t0 = clock()
     in_flight = collections.deque()            # (ids, sweeps) of enqueued epochs not yet retired, oldest first
     prefetch = getattr(executor, "prefetch", None)
+    # executors that keep idle contexts report their bytes: they count too
+    pooled = getattr(executor, "pooled_bytes", lambda: 0)
+    reusable = getattr(executor, "reusable", lambda run: False)
+    evict = getattr(executor, "evict", None)
 
     def now():
         return clock() - t0
@@ -166,7 +208,12 @@ def serve(requests, executor, hbm_budget=8 << 30, max_slots=4096, epoch_sweeps=1
                 results[rid] = Result(rid, run.L, run.sweeps, requests[rid].arrival, t, t,
                                       error="larger than the HBM budget")
                 continue
-            if used + need > hbm_budget:
+            extra = 0 if reusable(run) else need  # device bytes the admission adds
+            over = used + pooled() + extra - hbm_budget
+            if over > 0 and extra and evict is not None:
+                evict(over, run.L)
+                over = used + pooled() + extra - hbm_budget
+            if over > 0:
                 break
             waiting.popleft()
             active[rid] = [executor.create(run), run.sweeps, need, t]

@@ -172,3 +172,69 @@ def test_read_back_starts_right_after_the_last_epoch(depth):
     res, _ = serve.serve(reqs, ex, epoch_sweeps=32, clock=clk, sleep=clk.sleep, depth=depth)
     assert len(res) == len(reqs) and all(not r.error for r in res)
     assert len(ex.prefetched) == len(reqs)
+
+
+class PoolingExecutor(FakeExecutor):
+    """Keeps retired contexts for reuse by side, like the GPU executor."""
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.pool = {}       # side -> handles
+        self.order = []
+        self.evicted = 0
+        self.max_total = 0
+
+    def pooled_bytes(self):
+        return sum(self.bytes_for(W.Run(L=L)) * len(hs) for L, hs in self.pool.items())
+
+    def reusable(self, run):
+        return bool(self.pool.get(run.L))
+
+    def evict(self, nbytes, keep_side=None):
+        freed = 0
+        for h, L in list(self.order):
+            if freed >= nbytes:
+                break
+            if L == keep_side:
+                continue
+            self.order.remove((h, L))
+            self.pool[L].remove(h)
+            freed += self.bytes_for(W.Run(L=L))
+            self.evicted += 1
+        return freed
+
+    def create(self, run):
+        if self.pool.get(run.L):
+            h = self.pool[run.L].pop()
+            self.order.remove((h, run.L))
+            self.live[h] = run
+            self.done[h] = 0
+        else:
+            h = super().create(run)
+        self._track()
+        return h
+
+    def destroy(self, handle):
+        run = self.live.pop(handle)
+        self.pool.setdefault(run.L, []).append(handle)
+        self.order.append((handle, run.L))
+        self._track()
+
+    def _track(self):
+        live = sum(self.bytes_for(r) for r in self.live.values())
+        self.max_total = max(self.max_total, live + self.pooled_bytes())
+
+
+def test_pooled_contexts_count_against_the_budget():
+    """Idle contexts kept for reuse count against the HBM budget: the device
+    bytes held (admitted plus pooled) never pass it, and pooled contexts are
+    freed when an admission needs the room."""
+    clk = FakeClock()
+    ex = PoolingExecutor(clk)
+    reqs = _stream(n=60)
+    budget = 3 * 512 * 512
+    res, _ = serve.serve(reqs, ex, hbm_budget=budget, epoch_sweeps=32, clock=clk, sleep=clk.sleep)
+    assert all(not r.error for r in res if r.L * r.L <= budget)
+    assert ex.max_total <= budget
+    assert ex.evicted > 0
+
