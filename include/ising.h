@@ -58,6 +58,7 @@ extern "C" {
 #define ISING_ERANGE (-4)      /* sweep index would pass 2^32 - 1, or a buffer is too small */
 #define ISING_EUNSUPPORTED (-5) /* valid request the library cannot serve */
 #define ISING_ESTATE (-6)      /* context poisoned by an earlier device error */
+#define ISING_EIO (-7)         /* a file could not be written (the batch tuning cache) */
 
 #define ISING_MAX_L 65536u     /* counter word 0 holds site/8: L*L/8 must fit 32 bits */
 
@@ -201,9 +202,9 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * consecutive batches in stream order), with the batch plan ISING_BATCH_AUTO
  * picks (see ising_sweep_batch_plan): one persistent launch from a captured
  * graph in which each workgroup takes whole lattices, largest work first,
- * and runs all of their sweeps from its local memory, or, when some lattice
- * is too large for that, graph replays of passes that spread every lattice
- * over the whole GPU. The descriptors are staged through pinned host
+ * and runs all of their sweeps from its local memory, or, when that is
+ * predicted slower, graph replays of passes that spread every lattice over
+ * the whole GPU. The descriptors are staged through pinned host
  * memory by one copy kernel. Lattices may differ in L, J, h, T and seed;
  * each must satisfy L % 8 == 0 and have no pending device error. Contexts
  * are validated before anything is launched (all-or-nothing). The results
@@ -214,11 +215,11 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
 /* As ising_sweep_batch with an explicit batch plan:
  * ISING_BATCH_RESIDENT: one persistent launch, each workgroup runs whole
  *   lattices (every sweep) taken from a work queue, largest first. A lattice
- *   with h = 0 and side up to 1072 is held in the workgroup's local memory
- *   at one bit per site for all its sweeps, except that while the batch has
- *   fewer lattices than the launch has workgroups, those of side up to 256
- *   are held as bytes (lower latency per sweep); other lattices of side up
- *   to 256 are held there as bytes; larger ones are swept in global memory;
+ *   of side up to 1072 is held in the workgroup's local memory at one bit
+ *   per site for all its sweeps, except that lattices of side up to 256 are
+ *   held as bytes when h != 0 or while the batch has fewer lattices than
+ *   the launch has workgroups (lower latency per sweep); larger ones are
+ *   swept in global memory;
  *   (a single context's ising_sweep under the resident plan runs the same
  *   per-lattice code in one workgroup, launched directly);
  * ISING_BATCH_STEPPED: every sweep is one launch over the tiles of all
@@ -227,18 +228,66 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
  *   multiple of 16 the sweep is one pass (each lattice alternates between
  *   two buffers; a context without its second buffer gets one, L*L bytes,
  *   on first use); otherwise it is a launch per colour, in place;
- * ISING_BATCH_AUTO: resident when every lattice is held in local memory
- *   (side <= 256, or h = 0 and side <= 1072) and either every side is at
- *   most 256 or the resident launch keeps its workgroups (one per compute
- *   unit) busy enough: its makespan, lattices handed out largest work
- *   first, beats the stepped plan's time at 0.63 of the resident kernel's
- *   whole-GPU rate; else stepped.
- * Results are identical for every plan. */
+ * ISING_BATCH_AUTO: the plan predicted faster from the device's rates per
+ *   lattice class (see ising_batch_tune): the resident launch's makespan
+ *   (lattices handed out largest work first to its workgroups, one per
+ *   compute unit) against the stepped plan's summed time, each lattice's
+ *   work divided by its class's rate.
+ * The stepped plan's tile height (8, 16 or 32 rows, sides that are
+ * multiples of 16) is the one predicted fastest the same way. Results are
+ * identical for every plan and tile height. */
 #define ISING_BATCH_AUTO 0u
 #define ISING_BATCH_RESIDENT 1u
 #define ISING_BATCH_STEPPED 2u
 int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream,
                            uint32_t plan);
+
+/* Batch autotuner (the many-lattice workloads of Section 2.2). The batch
+ * plans' speeds depend on the lattices' sides and fields, so ISING_BATCH_AUTO
+ * and the stepped tile height are chosen from rates per class: a side band
+ * (up to 128, 256, 512, 1072, larger) and whether the field needs the
+ * general bit-packed update (h != 0). Rates are site updates per ns: for the
+ * resident plan, of one workgroup on one lattice (plus a fixed time per
+ * lattice: taking it from the queue and converting it to bits and back);
+ * for the stepped plan, of
+ * the whole GPU, per tile height (8, 16, 32); plus the stepped plan's least
+ * time per sweep. Until a device is tuned, built-in rates measured on an
+ * MI355X are used.
+ *
+ * ising_batch_tune times both plans on `device` with synthetic batches of
+ * each class (one lattice per resident workgroup; hot starts, J = 1, T over
+ * [1.5, 3.5], h = 0 or 0.05; a few seconds and up to 2 GiB of device
+ * memory, freed on return) and keeps the rates for that device in this
+ * process. cache_path (NULL: the ISING_TUNE_CACHE environment variable, if
+ * set and not empty) names a text file: rates stored there for the same
+ * device (architecture, compute units, launch sizes) are loaded instead of
+ * timed, unless flags has ISING_TUNE_RETIME; timed rates are written there.
+ * *from_cache (optional) is set to 1 when the rates were loaded.
+ * Synchronises the device. Errors: EINVAL (bad device or flags), EDEVICE,
+ * ENOMEM, EIO (the cache file could not be written; the rates are kept). */
+#define ISING_TUNE_RETIME 1u
+int ising_batch_tune(int device, const char* cache_path, uint32_t flags, int* from_cache);
+
+typedef struct ising_batch_rate {
+    uint32_t max_side;               /* class: sides up to this (the previous class's excluded) */
+    uint32_t field;                  /* class: 1 if the table needs the general bit-packed update */
+    double resident_per_workgroup;   /* site updates per ns, one resident workgroup */
+    double resident_fixed_ns;        /* resident: time per lattice besides its sweeps */
+    double stepped[3];               /* site updates per ns, whole GPU, tile rows 8, 16, 32 */
+} ising_batch_rate;
+
+/* The rates ISING_BATCH_AUTO uses on `device`: n >= 10 entries, ordered by
+ * side band then field; *tuned (optional) 1 if measured on this device in
+ * this process; *floor_ns (optional) the stepped plan's least time per
+ * sweep. Host only. */
+int ising_batch_rates(int device, ising_batch_rate* out, size_t n, int* tuned, double* floor_ns);
+
+/* The plan ISING_BATCH_AUTO would run for this batch (ISING_BATCH_RESIDENT
+ * or ISING_BATCH_STEPPED), the stepped tile height (0 when the stepped plan
+ * would not use the one-pass walk), and predicted_ns[0], [1] (optional):
+ * the predicted resident and stepped times. Host only. */
+int ising_batch_choice(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, uint32_t* plan,
+                       uint32_t* rows, double* predicted_ns);
 
 /* Plain time averages of a series window of n sweeps for an L x L lattice
  * with coupling J and field h (host only, no device work). */

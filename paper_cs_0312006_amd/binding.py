@@ -20,6 +20,7 @@ ISING_EDEVICE = -3
 ISING_ERANGE = -4
 ISING_EUNSUPPORTED = -5
 ISING_ESTATE = -6
+ISING_EIO = -7
 
 ISING_MAX_L = 65536
 ISING_STATIC_SCRATCH_PAIRS = 65536
@@ -34,6 +35,8 @@ ISING_PLAN_FUSED_ROWS = 5
 ISING_BATCH_AUTO = 0
 ISING_BATCH_RESIDENT = 1
 ISING_BATCH_STEPPED = 2
+
+ISING_TUNE_RETIME = 1
 
 ISING_OBS_HASH = 1
 ISING_OBS_SERIES = 2
@@ -53,6 +56,11 @@ class ising_obs(C.Structure):
 class ising_averages(C.Structure):
     _fields_ = [("n", C.c_uint64), ("e", C.c_double), ("e2", C.c_double), ("m", C.c_double),
                 ("abs_m", C.c_double), ("m2", C.c_double)]
+
+
+class ising_batch_rate(C.Structure):
+    _fields_ = [("max_side", C.c_uint32), ("field", C.c_uint32), ("resident_per_workgroup", C.c_double),
+                ("resident_fixed_ns", C.c_double), ("stepped", C.c_double * 3)]
 
 
 class perc_params(C.Structure):
@@ -95,6 +103,11 @@ SIGNATURES = {
     "ising_sweep_batch": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p]),
     "ising_sweep_batch_plan": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t, C.c_void_p,
                                          C.c_uint32]),
+    "ising_batch_tune": (C.c_int, [C.c_int, C.c_char_p, C.c_uint32, C.POINTER(C.c_int)]),
+    "ising_batch_rates": (C.c_int, [C.c_int, C.POINTER(ising_batch_rate), C.c_size_t, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_double)]),
+    "ising_batch_choice": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_uint64), C.c_size_t,
+                                     C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_double)]),
     "ising_series_averages": (C.c_int, [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_double,
                                         C.c_double, C.POINTER(ising_averages)]),
     "ising_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
@@ -266,6 +279,34 @@ def ising_sweep_batch_plan(ctxs, n_sweeps, plan, stream=None):
     ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
     _check(lib().ising_sweep_batch_plan(arr, ns, k, stream, int(plan)), "ising_sweep_batch_plan",
            ctxs[0] if ctxs else None)
+
+
+def ising_batch_tune(device=0, cache_path=None, flags=0):
+    """Returns True when the rates were loaded from cache_path."""
+    hit = C.c_int(0)
+    path = os.fsencode(cache_path) if cache_path is not None else None
+    _check(lib().ising_batch_tune(int(device), path, int(flags), C.byref(hit)), "ising_batch_tune")
+    return bool(hit.value)
+
+
+def ising_batch_rates(device=0):
+    """(list of dicts per class, tuned, floor_ns)."""
+    out = (ising_batch_rate * 10)()
+    tuned, floor = C.c_int(0), C.c_double(0.0)
+    _check(lib().ising_batch_rates(int(device), out, 10, C.byref(tuned), C.byref(floor)), "ising_batch_rates")
+    rows = [{"max_side": r.max_side, "field": r.field, "resident_per_workgroup": r.resident_per_workgroup,
+             "resident_fixed_ns": r.resident_fixed_ns, "stepped": list(r.stepped)} for r in out]
+    return rows, bool(tuned.value), floor.value
+
+
+def ising_batch_choice(ctxs, n_sweeps):
+    """(plan, stepped tile rows, (predicted resident ns, predicted stepped ns))."""
+    k = len(ctxs)
+    arr = (C.c_void_p * k)(*ctxs)
+    ns = (C.c_uint64 * k)(*[int(n) for n in n_sweeps])
+    plan, rows, pred = C.c_uint32(), C.c_uint32(), (C.c_double * 2)()
+    _check(lib().ising_batch_choice(arr, ns, k, C.byref(plan), C.byref(rows), pred), "ising_batch_choice")
+    return plan.value, rows.value, (pred[0], pred[1])
 
 
 def ising_series_averages(bond, mag, L, J=1.0, h=0.0):

@@ -8,9 +8,11 @@
 // the kernel is persistent: no workgroup waits on another.
 //
 // Where a lattice lives while it is swept:
-//   - h = 0 lattices whose two colour planes fit this workgroup's LDS at one
-//     bit per site (sides up to 1072) are converted to bits, swept there for
-//     all their sweeps and converted back (the bit-packed path below);
+//   - lattices whose two colour planes fit this workgroup's LDS at one bit
+//     per site (sides up to 1072) are converted to bits, swept there for all
+//     their sweeps and converted back (the bit-packed path below): h = 0
+//     lattices whenever the host asks for it, h != 0 lattices when they do
+//     not fit as bytes;
 //   - other lattices of at most 64 KiB are copied to LDS as bytes;
 //   - the rest are swept in place in global memory.
 #include <hip/hip_runtime.h>
@@ -134,6 +136,14 @@ __device__ __forceinline__ void run_lattice(const LdsTable& lt, const BatchItem&
 // thresholds (bit by bit, shifted into two masks of failed compares), and a
 // site flips unless it is in such a class and its compare failed. The draws and thresholds
 // are those of the byte kernels, so the results are the same bit for bit.
+//
+// For h != 0 the threshold depends on the site's spin s as well: the class
+// is (s, m), ten of them, with threshold thr(code 8 s + n), n = s ? 4 - m :
+// m up neighbours. A bit-sliced count of the four disagreement masks gives
+// the five masks "exactly m disagree"; per class that is never accepted
+// (threshold 0) its sites are rejected outright, per class that is always
+// accepted (threshold 2^32) nothing is done, and per remaining class its
+// sites' draws are compared with its threshold as above.
 
 // acc = 2 acc + (r > thr_m1): the borrow of thr_m1 - r shifted in, two VALU
 // operations (the compiler's own form of this takes three).
@@ -175,10 +185,56 @@ struct BitsLattice {
     uint32_t thra_m1, thrb_m1;  // class thresholds minus one (when not never)
     bool never_a, never_b;
     bool ferro;         // classes A, B are m = 1, 0 (else m = 3, 4)
+    // general classes (h != 0): class (s, m) is entry 5 s + m
+    uint32_t cls_m1[10];    // threshold minus one, for the compared classes
+    uint32_t cls_kind[10];  // kClassAlways, kClassNever or kClassCompare
 };
 
+constexpr uint32_t kClassAlways = 0, kClassNever = 1, kClassCompare = 2;
+
+// Rejection mask of one class over the 32 draws of a word (bit 4 j + b set
+// when draw b of quad j is at or above the class threshold).
+__device__ __forceinline__ uint32_t class_rejects(const uint4 (&r)[8], uint32_t thr_m1) {
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 7; j >= 0; --j) {
+        acc = shift_in_reject(acc, r[j].w, thr_m1);
+        acc = shift_in_reject(acc, r[j].z, thr_m1);
+        acc = shift_in_reject(acc, r[j].y, thr_m1);
+        acc = shift_in_reject(acc, r[j].x, thr_m1);
+    }
+    return acc;
+}
+
+// Sites of a word that keep their spin, for the general (s, m) classes.
+__device__ __forceinline__ uint32_t general_rejects(const BitsLattice& bl, uint32_t own, uint32_t a, uint32_t b,
+                                                    uint32_t d, uint32_t e, uint32_t q0, uint32_t t, uint32_t c,
+                                                    uint32_t k0, uint32_t k1) {
+    uint4 r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = philox(q0 + (uint32_t)j, t, c, 0u, k0, k1);
+    // bit-sliced m = a + b + d + e: ones, twos and fours planes
+    const uint32_t x = a ^ b, y = a & b, z = d ^ e, w = d & e;
+    const uint32_t ones = x ^ z, cz = x & z;
+    const uint32_t twos = y ^ w ^ cz;
+    const uint32_t fours = (y & w) | (cz & (y ^ w));
+    const uint32_t exactly[5] = {~(ones | twos | fours), ones & ~twos, twos & ~ones, ones & twos, fours};
+    uint32_t reject = 0;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const uint32_t sm = sp ? own : ~own;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const uint32_t kind = bl.cls_kind[5 * sp + m];
+            if (kind == kClassNever) reject |= sm & exactly[m];
+            else if (kind == kClassCompare) reject |= sm & exactly[m] & class_rejects(r, bl.cls_m1[5 * sp + m]);
+        }
+    }
+    return reject;
+}
+
 // Colour pass c of sweep t over the bit planes at lat (plane c at c * L * Wr).
-template <bool OBS>
+template <bool OBS, bool GENERAL>
 __device__ __forceinline__ void bits_pass(uint32_t* __restrict__ lat, const BitsLattice& bl, uint32_t c,
                                           uint32_t t, uint32_t k0, uint32_t k1, uint32_t& mis, uint32_t& ups) {
     const uint32_t L = bl.L, Wr = bl.Wr, Hw = bl.Hw;
@@ -211,23 +267,29 @@ __device__ __forceinline__ void bits_pass(uint32_t* __restrict__ lat, const Bits
         const uint32_t s_up = (O >> 1) | ((On & 1u) << top);
         const uint32_t s_dn = ((O << 1) | ((Op >> top_p) & 1u)) & valid;
         const uint32_t S = ((i + c) & 1u) ? s_up : s_dn;
-        uint32_t ra, rb;
-        bits_compares(q0, t, c, k0, k1, bl.thra_m1, bl.thrb_m1, ra, rb);
-        if (bl.never_a) ra = 0xffffffffu;
-        if (bl.never_b) rb = 0xffffffffu;
-        // disagreement masks and the two classes
+        // disagreement masks
         const uint32_t a = own ^ U, b = own ^ D, d = own ^ O, e = own ^ S;
-        const uint32_t odd = a ^ b ^ d ^ e;
-        const uint32_t pair = (a & b) | (d & e);
-        uint32_t ea, eb;
-        if (bl.ferro) {
-            ea = odd & ~pair;       // exactly one disagrees
-            eb = ~(a | b | d | e);  // none
+        uint32_t reject;
+        if (GENERAL) {
+            reject = general_rejects(bl, own, a, b, d, e, q0, t, c, k0, k1);
         } else {
-            ea = odd & pair;        // exactly three
-            eb = a & b & d & e;     // all four
+            uint32_t ra, rb;
+            bits_compares(q0, t, c, k0, k1, bl.thra_m1, bl.thrb_m1, ra, rb);
+            if (bl.never_a) ra = 0xffffffffu;
+            if (bl.never_b) rb = 0xffffffffu;
+            // the two classes
+            const uint32_t odd = a ^ b ^ d ^ e;
+            const uint32_t pair = (a & b) | (d & e);
+            uint32_t ea, eb;
+            if (bl.ferro) {
+                ea = odd & ~pair;       // exactly one disagrees
+                eb = ~(a | b | d | e);  // none
+            } else {
+                ea = odd & pair;        // exactly three
+                eb = a & b & d & e;     // all four
+            }
+            reject = (ea & ra) | (eb & rb);
         }
-        const uint32_t reject = (ea & ra) | (eb & rb);
         const uint32_t nw = own ^ (valid & ~reject);
         own_p[ro + k] = nw;
         if (OBS) {
@@ -284,7 +346,7 @@ __device__ __forceinline__ BitsLattice bits_setup(const BatchItem& it) {
     const uint32_t H = 4u * it.Hw;
     bl.hb = (H - 1u) & 31u;
     bl.last_valid = bl.hb == 31u ? 0xffffffffu : ((1u << (bl.hb + 1u)) - 1u);
-    bl.ferro = it.bits == 1u;
+    bl.ferro = it.bits == 1u;  // (mode 3: the general classes below)
     const uint32_t ma = bl.ferro ? 1u : 3u, mb = bl.ferro ? 0u : 4u;
     auto thr64 = [&](uint32_t m) {
         const uint32_t code = 8u + (4u - m);
@@ -295,10 +357,21 @@ __device__ __forceinline__ BitsLattice bits_setup(const BatchItem& it) {
     bl.never_b = tb == 0;
     bl.thra_m1 = ta == 0 ? 0u : (uint32_t)(ta - 1);
     bl.thrb_m1 = tb == 0 ? 0u : (uint32_t)(tb - 1);
+#pragma unroll
+    for (uint32_t sp = 0; sp < 2; ++sp) {
+#pragma unroll
+        for (uint32_t m = 0; m < 5; ++m) {
+            const uint32_t code = 8u * sp + (sp ? 4u - m : m);
+            const uint64_t thr = ((uint64_t)it.table.thr_hi[code] << 32) | it.table.thr_lo[code];
+            bl.cls_kind[5 * sp + m] = thr == 0 ? kClassNever : (thr >> 32) ? kClassAlways : kClassCompare;
+            bl.cls_m1[5 * sp + m] = thr == 0 ? 0u : (uint32_t)(thr - 1);
+        }
+    }
     return bl;
 }
 
 // All sweeps of one bit-packed lattice (already in LDS at lat).
+template <bool GENERAL>
 __device__ void run_bits(uint32_t* __restrict__ lat, const BatchItem& it, uint32_t (*part)[kMaxWaves][2]) {
     const BitsLattice bl = bits_setup(it);
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -320,9 +393,9 @@ __device__ void run_bits(uint32_t* __restrict__ lat, const BatchItem& it, uint32
     for (uint32_t s = 0; s < it.n; ++s) {
         const uint32_t t = it.t0 + s;
         uint32_t mis = 0, ups = 0;
-        bits_pass<false>(lat, bl, 0u, t, it.k0, it.k1, mis, ups);
+        bits_pass<false, GENERAL>(lat, bl, 0u, t, it.k0, it.k1, mis, ups);
         __syncthreads();
-        bits_pass<true>(lat, bl, 1u, t, it.k0, it.k1, mis, ups);
+        bits_pass<true, GENERAL>(lat, bl, 1u, t, it.k0, it.k1, mis, ups);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             mis += __shfl_xor(mis, off, 64);
@@ -362,7 +435,8 @@ __device__ __forceinline__ void batch_one(const BatchItem& it, LdsTable& lt, uin
     if (it.bits && 2u * bit_words * 4u <= kBatchBitsLdsBytes && it.n > 0) {
         bits_load(lat, it, (it.Hw + 7u) / 8u);
         __syncthreads();
-        run_bits(lat, it, red);
+        if (it.bits == 3u) run_bits<true>(lat, it, red);
+        else run_bits<false>(lat, it, red);
         __syncthreads();
         bits_store(lat, it, (it.Hw + 7u) / 8u);
     } else if (2u * plane_words * 4u <= kBatchLdsBytes && it.n > 0) {
@@ -426,12 +500,12 @@ uint32_t bits_mode(const AcceptTable& at) {
     uint64_t T[5];
     for (uint32_t m = 0; m < 5; ++m) {
         T[m] = thr(8u + (4u - m));    // up spin, 4 - m up neighbours
-        if (thr(m) != T[m]) return 0;  // down spin, m up neighbours
+        if (thr(m) != T[m]) return 3;  // down spin, m up neighbours
     }
-    if (T[2] != one) return 0;
+    if (T[2] != one) return 3;
     if (T[3] == one && T[4] == one) return 1;
     if (T[0] == one && T[1] == one) return 2;
-    return 0;
+    return 3;
 }
 
 bool bits_fit(uint32_t L) {

@@ -270,6 +270,17 @@ uint32_t engine_resident_slots(int dev) {
     return e.grid;
 }
 
+uint32_t engine_fused_slots(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return 0;
+    Engine& e = g_engines[dev];
+    std::lock_guard<std::mutex> g(e.mu);
+    if (init_engine(e) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return e.fslots;
+}
+
 void fill_batch_item(const ising_ctx* c, uint64_t n, bool stepped, BatchItem& it) {
     const Planes pl = ctx_planes(c);
     it.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
@@ -293,7 +304,8 @@ void fill_batch_item(const ising_ctx* c, uint64_t n, bool stepped, BatchItem& it
     it.table = c->table;
 }
 
-int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped) {
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped,
+               uint32_t rows_wanted) {
     int dev = ctxs[0]->device;
     if (dev < 0 || dev >= kMaxDevices) return ISING_EINVAL;
     // series room first (may synchronise the contexts' streams)
@@ -352,7 +364,10 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
             it.q0 = reinterpret_cast<uint32_t*>(alt.p[0]);
             it.q1 = reinterpret_cast<uint32_t*>(alt.p[1]);
         }
-        it.bits = (!stepped && bits_fit(c->L) && (saturated || !bytes_fit(c->L))) ? bits_mode(c->table) : 0u;
+        // the general (h != 0) bit update costs more per site than the byte
+        // kernel: only for lattices that do not fit as bytes
+        const uint32_t mode = bits_fit(c->L) ? bits_mode(c->table) : 0u;
+        it.bits = (!stepped && mode && (!bytes_fit(c->L) || (saturated && mode != 3u))) ? mode : 0u;
         work[k] = (uint64_t)c->L * c->L * n[k];
     }
     uint64_t max_n = 0;
@@ -367,10 +382,10 @@ int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStrea
         e.h_hdr->count = live;
         e.h_hdr->head = 0;
     } else {
-        // fused walk: the tallest tiles (32 rows) that still give every wave
-        // slot of the GPU about two tiles; fewer rows for a few large lattices
-        uint32_t rows = 32u;
-        if (fused) {
+        // fused walk: the tile height asked for, else the tallest tiles (32
+        // rows) that still give every wave slot of the GPU about two tiles
+        uint32_t rows = rows_wanted ? rows_wanted : 32u;
+        if (fused && !rows_wanted) {
             const uint64_t want = 2ull * e.fslots;
             for (; rows > 8u; rows /= 2u) {
                 uint64_t tiles = 0;

@@ -121,7 +121,7 @@ struct BatchItem {
     uint32_t* q1;
     int64_t* series;    // 2 int64 per sweep, for sweeps t0 .. t0+n-1
     uint32_t L, Hw, cw, t0, n, k0, k1, exact;
-    uint32_t bits;      // resident batch: 1 / 2 = bit-packed in LDS (see bits_mode), 0 = not
+    uint32_t bits;      // resident batch: 1 / 2 / 3 = bit-packed in LDS (see bits_mode), 0 = not
     uint32_t pad;
     AcceptTable table;
 };
@@ -134,14 +134,15 @@ struct BatchHeader {
 // Lattices whose two planes fit in this many bytes run from LDS in the
 // resident batch kernel (256 x 256 sites).
 constexpr uint32_t kBatchLdsBytes = 65536;
-// h = 0 lattices whose two planes fit in this many bytes at one bit per site
-// run bit-packed from LDS in the resident batch kernel (sides up to 1072).
+// Lattices whose two planes fit in this many bytes at one bit per site run
+// bit-packed from LDS in the resident batch kernel (sides up to 1072).
 constexpr uint32_t kBatchBitsLdsBytes = 147456;
 
-// Bit-packed mode of a lattice's acceptance table: the threshold must depend
-// only on the number m of disagreeing neighbours (h = 0), with m = 2, 3, 4
-// always accepted (1: J >= 0) or m = 0, 1, 2 always accepted (2: J < 0);
-// else 0.
+// Bit-packed update of a lattice's acceptance table: when the threshold
+// depends only on the number m of disagreeing neighbours (h = 0), with
+// m = 2, 3, 4 always accepted (1: J >= 0) or m = 0, 1, 2 always accepted
+// (2: J < 0), two class compares per site; otherwise (3) one compare per
+// (spin, m) class that is neither always nor never accepted.
 uint32_t bits_mode(const AcceptTable& at);
 // Whether an L x L lattice fits the bit-packed LDS area.
 bool bits_fit(uint32_t L);

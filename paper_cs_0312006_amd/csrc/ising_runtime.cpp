@@ -76,29 +76,6 @@ static std::map<uint32_t, Plan> g_tuned;
 
 // Sides up to this run all their sweeps inside one workgroup by default.
 constexpr uint32_t kResidentMaxL = 128;
-// Batches whose largest side is at most this use the resident kernel.
-constexpr uint32_t kResidentBatchMaxL = 256;
-// Stepped plan throughput over the resident plan's with every workgroup
-// busy, on the batched configuration (1024 lattices of sides 32 to 1024:
-// ~1480 against ~2320 site updates/ns).
-constexpr double kSteppedVsResident = 0.63;
-
-// Largest workgroup load when the lattices' works are handed out largest
-// first to the least loaded of `slots` workgroups (the resident queue's
-// order).
-static uint64_t resident_makespan(std::vector<uint64_t> work, uint32_t slots) {
-    std::sort(work.begin(), work.end(), std::greater<uint64_t>());
-    std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> load;
-    for (uint32_t k = 0; k < slots; ++k) load.push(0);
-    uint64_t span = 0;
-    for (uint64_t w : work) {
-        const uint64_t l = load.top() + w;
-        load.pop();
-        load.push(l);
-        span = std::max(span, l);
-    }
-    return span;
-}
 // Fused tiles wanted per launch (one wave each) before a taller/wider tile is used.
 constexpr uint32_t kFusedMinTiles = 16384;
 // The autotuner replaces the default plan only when a candidate is faster
@@ -722,35 +699,13 @@ int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, siz
             if (ctxs[j] == c) return ISING_EINVAL;  // one context may appear once
     }
     if (hipSetDevice(dev) != hipSuccess) return ISING_EDEVICE;
-    bool stepped = plan == ISING_BATCH_STEPPED;
-    if (plan == ISING_BATCH_AUTO) {
-        // One workgroup per lattice when every lattice is held in local
-        // memory and either every lattice is small (a workgroup sweeps it in
-        // a few microseconds) or the resident launch keeps its workgroups
-        // busy: its makespan, with the lattices handed out largest first,
-        // must beat the stepped plan, which runs at about kSteppedVsResident
-        // of the resident kernel's whole-GPU rate. A few large lattices
-        // would each leave one compute unit doing the work of the whole GPU.
-        bool local = true, small = true;
-        std::vector<uint64_t> work;
-        uint64_t total = 0;
-        for (size_t k = 0; k < count; ++k) {
-            const ising_ctx* c = ctxs[k];
-            if (n_sweeps[k] == 0) continue;
-            work.push_back((uint64_t)c->L * c->L * n_sweeps[k]);
-            total += work.back();
-            if (c->L > kResidentBatchMaxL) {
-                small = false;
-                if (!(bits_fit(c->L) && bits_mode(c->table) != 0)) local = false;
-            }
-        }
-        stepped = !local;
-        if (local && !small) {
-            const uint32_t slots = engine_resident_slots(dev);
-            stepped = slots == 0 || (double)resident_makespan(work, slots) * slots * kSteppedVsResident >= (double)total;
-        }
-    }
-    return engine_run(ctxs, n_sweeps, count, static_cast<hipStream_t>(stream), stepped);
+    // the plan (AUTO) and the stepped tile height predicted fastest from
+    // the device's per-class rates
+    BatchChoice ch;
+    const int rc = batch_choose(ctxs, n_sweeps, count, dev, &ch);
+    if (rc != ISING_OK) return rc;
+    const bool stepped = plan == ISING_BATCH_AUTO ? ch.stepped : plan == ISING_BATCH_STEPPED;
+    return engine_run(ctxs, n_sweeps, count, static_cast<hipStream_t>(stream), stepped, ch.rows);
 }
 
 static int ensure_canonical(ising_ctx* ctx) {
@@ -1302,6 +1257,7 @@ const char* ising_strerror(int code) {
         case ISING_ERANGE: return "out of range";
         case ISING_EUNSUPPORTED: return "unsupported by this library";
         case ISING_ESTATE: return "context poisoned by an earlier device error";
+        case ISING_EIO: return "file could not be written";
         default: return "unknown error";
     }
 }

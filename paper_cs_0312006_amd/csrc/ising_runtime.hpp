@@ -93,10 +93,25 @@ int ctx_fail(ising_ctx* ctx, hipError_t e, const char* where = "");
 // Run a batch on stream s (nullptr: the engine's own stream on the
 // contexts' device), ordered after every context's earlier work and before
 // its later work.
-int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped);
+// rows: the stepped fused walk's tile height (8, 16 or 32; 0: the engine's
+// own choice).
+int engine_run(ising_ctx* const* ctxs, const uint64_t* n, size_t count, hipStream_t s, bool stepped,
+               uint32_t rows = 0);
 // Workgroups of the persistent resident launch on device dev (lattices it
 // runs at once); 0 if the engine cannot be set up.
 uint32_t engine_resident_slots(int dev);
+// Waves of the stepped fused walk resident at once on device dev.
+uint32_t engine_fused_slots(int dev);
+
+// Batch plan model (ising_batch_tune.cpp): the plan and stepped tile height
+// predicted fastest for a batch, from the device's measured (or built-in)
+// per-class rates, with both predictions in ns.
+struct BatchChoice {
+    bool stepped;
+    uint32_t rows;
+    double resident_ns, stepped_ns;
+};
+int batch_choose(ising_ctx* const* ctxs, const uint64_t* n, size_t count, int dev, BatchChoice* out);
 // Descriptor of context c for n sweeps from its current state: lattice
 // planes, series slots after the pending ones, draw key, table, words per
 // thread (stepped or resident). The fused walk's second planes and the

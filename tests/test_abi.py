@@ -136,3 +136,22 @@ def test_percolation_rejects_bad_parameters(b):
 
 def test_device_error_of_null_context_is_empty(b):
     assert b.lib().ising_device_error(None) == b""
+
+
+def test_batch_rates_before_tuning(b):
+    """Until a device is tuned the batch model uses the built-in rates: ten
+    classes (five side bands, without and with a field), every rate
+    positive, the bands in increasing side order, the last open-ended."""
+    rows, tuned, floor_ns = b.ising_batch_rates(0)
+    assert not tuned and floor_ns > 0
+    assert [r["field"] for r in rows] == [0, 1] * 5
+    sides = [r["max_side"] for r in rows[::2]]
+    assert sides == [128, 256, 512, 1072, b.ISING_MAX_L]
+    for r in rows:
+        assert r["resident_per_workgroup"] > 0 and all(x > 0 for x in r["stepped"])
+    lib = b.lib()
+    out = (b.ising_batch_rate * 10)()
+    assert lib.ising_batch_rates(0, out, 9, None, None) == b.ISING_EINVAL
+    assert lib.ising_batch_rates(-1, out, 10, None, None) == b.ISING_EINVAL
+    assert lib.ising_batch_tune(0, None, 2, None) == b.ISING_EINVAL  # unknown flag
+    assert b.lib().ising_strerror(b.ISING_EIO)

@@ -200,6 +200,42 @@ def test_batch_bit_packed_couplings_and_sides(b, o):
                       f"bit-packed L={r.L} J={r.J} T={r.T}")
 
 
+def test_batch_bit_packed_field_classes(b, o):
+    """h != 0 lattices too large to hold as bytes (sides 264 to 1080) run
+    bit-packed with one compare per (spin, m) class: weak and strong fields
+    of both signs, J > 0 and J < 0, classes never accepted (T = 0.05, and a
+    field so strong that some classes are), classes always accepted, and
+    one lattice with every threshold 2^32 (T = 1e300). Each result equals
+    the oracle's run of that lattice alone; the single-context resident plan
+    takes the same path."""
+    runs = [W.Run(L=264, J=1.0, h=0.05, T=2.269185, seed=11, p_up=0.5, sweeps=40),
+            W.Run(L=320, J=1.0, h=-0.3, T=1.5, seed=12, p_up=1.0, sweeps=30),
+            W.Run(L=512, J=1.0, h=3.0, T=2.0, seed=13, p_up=0.0, sweeps=20),
+            W.Run(L=392, J=-1.0, h=0.2, T=1.8, seed=14, p_up=0.5, sweeps=25),
+            W.Run(L=600, J=1.0, h=0.1, T=0.05, seed=15, p_up=0.5, sweeps=12),
+            W.Run(L=272, J=-0.5, h=-5.0, T=0.3, seed=16, p_up=0.5, sweeps=15),
+            W.Run(L=1024, J=1.0, h=0.05, T=3.0, seed=17, p_up=0.5, sweeps=8),
+            W.Run(L=1072, J=1.0, h=0.5, T=1e300, seed=18, p_up=0.5, sweeps=5),
+            W.Run(L=1080, J=2.0, h=-0.7, T=2.5, seed=19, p_up=1.0, sweeps=4)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    try:
+        G.log("field bit-packed batch of 9 (RESIDENT)")
+        b.ising_sweep_batch_plan(ctxs, [r.sweeps for r in runs], b.ISING_BATCH_RESIDENT)
+        for r, ctx in zip(runs, ctxs):
+            obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            spins = b.ising_copy_spins(ctx, r.L)
+            G.log(f"field bit-packed: L={r.L} J={r.J} h={r.h} T={r.T} vs oracle")
+            G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r),
+                          f"field bit-packed L={r.L} J={r.J} h={r.h} T={r.T}")
+    finally:
+        for ctx in ctxs:
+            b.ising_destroy(ctx)
+    r = runs[3]
+    G.log("field bit-packed: single-context resident plan L=392")
+    G.assert_same(_run_plan(b, r, b.ISING_PLAN_RESIDENT, chunks=[7, 18]), G.oracle_run(o, r),
+                  "single-context resident, field classes")
+
+
 def test_batch_bit_packed_saturated_batch(b, o):
     """A resident batch with more lattices (400) than the launch has
     workgroups, so every h = 0 lattice that fits local memory as bits is
