@@ -116,6 +116,11 @@ def kernel_sources_hash(files=HEADLINE_FILES):
 CREUTZ_FILES = ("ising_creutz_fused.hip", "ising_creutz.hpp", "ising_device.hpp", "ising_launch.hpp")
 
 
+def progress(msg):
+    """One line on stderr per finished leg (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def host_cores():
     try:
         return max(1, len(os.sched_getaffinity(0)))
@@ -183,14 +188,23 @@ def cpu_baseline(run, sweeps, B0, M0):
 
 def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
     """1024 lattices (L = 32 + 16 U{0..62}, T ~ U[1.5, 3.5], h = 0, seed =
-    index) in one persistent launch; comparator: one sweep call per lattice
-    on a random sample, back to back on one stream."""
-    import numpy as np
+    index) in one batch call with the given plan (0: the tuned AUTO plan).
+    Comparator (sample > 0): one lattice of every side (the first of that
+    side in the generator's order), each on its own context with the
+    single-lattice plan ising_tune picks for its side (graph replays for the
+    two-pass plan), its whole run as one ising_sweep call, back to back on
+    one stream; per-lattice device times give a rate per side, from which
+    the whole configuration's time one lattice at a time is estimated."""
     from paper_cs_0312006_amd import workloads as W
     runs = W.batched(count=count, sweeps=sweeps)
     total = sum(r.attempts() for r in runs)
+    firsts = {}
+    for k, r in enumerate(runs):
+        firsts.setdefault(r.L, k)
+    picked = sorted(firsts.values()) if sample > 0 else []
     ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=stream.cuda_stream) for r in runs]
     try:
+        choice = b.ising_batch_choice(ctxs, [r.sweeps for r in runs])
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -200,58 +214,52 @@ def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
         e1.synchronize()
         ms = e0.elapsed_time(e1)
         hashes = {}
-        for k in range(min(64, len(runs))):
+        for k in sorted(set(range(min(64, len(runs)))) | set(picked)):
             obs, _, _ = b.ising_observables(ctxs[k], b.ISING_OBS_HASH | b.ISING_OBS_SERIES)
             hashes[k] = obs.lattice_hash
     finally:
         for c in ctxs:
             b.ising_destroy(c)
+    plan_run = plan or choice[0]
     res = {"lattices": count, "sweeps": sweeps, "attempts": total,
            "value": total / ms / 1e6, "unit": "spin-update attempts/ns", "ms": ms,
-           "plan": {0: "auto", 1: "resident", 2: "stepped"}[plan]}
-    if sample <= 0:
+           "plan": {1: "resident", 2: "stepped"}[plan_run] + (" (auto)" if plan == 0 else ""),
+           "model_prediction_ms": {"resident": choice[2][0] / 1e6, "stepped": choice[2][1] / 1e6,
+                                   "stepped_tile_rows": choice[1]}}
+    if not picked:
         return res, hashes
-    # comparator on the first `sample` lattices (the generator's order is random)
-    sub = runs[:sample]
-    sub_attempts = sum(r.attempts() for r in sub)
+    sub = [runs[k] for k in picked]
     ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=stream.cuda_stream) for r in sub]
     same = True
     try:
-        torch.cuda.synchronize()
-        e0.record(stream)
+        plans = {}
         for c, r in zip(ctxs, sub):
+            b.ising_tune(c, 16)  # the side's plan, remembered for later contexts of that side
+            plans[r.L] = b.ising_plan_info(c)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(sub) + 1)]
+        ev[0].record(stream)
+        for k, (c, r) in enumerate(zip(ctxs, sub)):
             b.ising_sweep(c, r.sweeps)
-        e1.record(stream)
-        e1.synchronize()
-        ms_solo = e0.elapsed_time(e1)
-        for k, c in enumerate(ctxs):
+            ev[k + 1].record(stream)
+        ev[-1].synchronize()
+        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(len(sub))]
+        for k, c in zip(picked, ctxs):
             obs, _, _ = b.ising_observables(c, b.ISING_OBS_HASH | b.ISING_OBS_SERIES)
             same &= obs.lattice_hash == hashes[k]
     finally:
         for c in ctxs:
             b.ising_destroy(c)
-    res["one_launch_per_lattice"] = {"lattices": len(sub), "attempts": sub_attempts, "ms": ms_solo,
-                                     "value": sub_attempts / ms_solo / 1e6,
-                                     "results_identical_to_batched": bool(same)}
-    res["speedup_vs_one_launch_per_lattice"] = (total / ms) / (sub_attempts / ms_solo)
-    # the same sample on 8 streams (each lattice on its own context stream,
-    # calls issued round-robin, then all synchronised): labelled comparator
-    streams = [torch.cuda.Stream() for _ in range(8)]
-    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, stream=streams[k % 8].cuda_stream)
-            for k, r in enumerate(sub)]
-    try:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for c, r in zip(ctxs, sub):
-            b.ising_sweep(c, r.sweeps)
-        torch.cuda.synchronize()
-        ms_multi = (time.perf_counter() - t0) * 1e3
-    finally:
-        for c in ctxs:
-            b.ising_destroy(c)
-    res["one_launch_per_lattice_8_streams"] = {"lattices": len(sub), "ms": ms_multi,
-                                               "value": sub_attempts / ms_multi / 1e6,
-                                               "clock": "host, around issue and final synchronise"}
+    rate = {r.L: r.attempts() / t / 1e6 for r, t in zip(sub, per)}  # attempts/ns per side
+    est_ms = sum(r.attempts() / rate[r.L] for r in runs) / 1e6
+    sub_attempts = sum(r.attempts() for r in sub)
+    res["one_launch_per_lattice"] = {
+        "sample": f"one lattice per side ({len(sub)} sides, 32 to 1024), each on its own tuned single-lattice plan",
+        "lattices": len(sub), "attempts": sub_attempts, "ms": sum(per), "value": sub_attempts / sum(per) / 1e6,
+        "plans_by_side": {str(L): {"kind": p[0], "chunk_words": p[1], "tile_rows": p[2]} for L, p in plans.items()},
+        "whole_config_estimate_ms": est_ms, "whole_config_estimate_value": total / est_ms / 1e6,
+        "results_identical_to_batched": bool(same)}
+    res["speedup_vs_one_launch_per_lattice"] = est_ms / ms
     return res, hashes
 
 
@@ -306,10 +314,49 @@ def run_served(rates, count, epoch_sweeps):
         finally:
             ex.close()
         s = serve.summarize(res, stats["makespan_s"])
+        progress(f"served {rate:g}/s: {s['attempts_per_ns']:.0f} attempts/ns")
         s.update({"rate_per_s": rate, "epochs": stats["epochs"], "epoch_sweeps": epoch_sweeps,
                   "offered_attempts_per_ns": rate * sum(r.run.attempts() for r in reqs) / len(reqs) / 1e9})
         out.append(s)
     return out
+
+
+def run_fifo(b, rate, count):
+    """Comparator for the served leg: the same request stream, one request
+    at a time in arrival order, each on its own context with the
+    single-lattice plan ising_tune picked for its side (every side tuned
+    before the stream starts), its sweeps as one ising_sweep call, the
+    series read back, the context destroyed; p50/p99 from scheduled arrival
+    to result on the host."""
+    from paper_cs_0312006_amd import serve
+    from paper_cs_0312006_amd import workloads as W
+    reqs = W.request_stream(rate, count=count)
+    for L in sorted({q.run.L for q in reqs}):
+        ctx = b.ising_create(L)
+        try:
+            b.ising_tune(ctx, 16)
+        finally:
+            b.ising_destroy(ctx)
+    results = []
+    t0 = time.perf_counter()
+    for k, q in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if now < q.arrival:
+            time.sleep(q.arrival - now)
+        start = time.perf_counter() - t0
+        r = q.run
+        ctx = b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up)
+        try:
+            b.ising_sweep(ctx, r.sweeps)
+            obs, _, _ = b.ising_observables(ctx, b.ISING_OBS_SERIES)
+        finally:
+            b.ising_destroy(ctx)
+        results.append(serve.Result(k, r.L, r.sweeps, q.arrival, start, time.perf_counter() - t0,
+                                    bond_sum=obs.bond_sum, mag_sum=obs.mag_sum))
+    s = serve.summarize(results, max(x.done for x in results))
+    progress(f"FIFO {rate:g}/s: {s['attempts_per_ns']:.0f} attempts/ns")
+    s.update({"rate_per_s": rate, "comparator": "one request at a time (FIFO), tuned single-lattice plans"})
+    return s
 
 
 def run_creutz(b, torch, stream, sweeps, metropolis_value, cpu=True):
@@ -539,7 +586,11 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=8,
                     help="oracle sweeps of the headline lattice for cpu_baseline (about 10 s on 16 cores)")
     ap.add_argument("--batched-sweeps", type=int, default=10000)
-    ap.add_argument("--batched-sample", type=int, default=64)
+    ap.add_argument("--batched-sample", type=int, default=1,
+                    help="0: no one-launch-per-lattice comparator (else one lattice per side)")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="use the built-in batch rates instead of timing them first")
+    ap.add_argument("--no-fifo", action="store_true", help="skip the one-request-at-a-time served comparator")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-rates", type=str, default="100,200,500,1000,2000,5000")
     ap.add_argument("--served-subsat-rate", type=float, default=10.0,
@@ -550,7 +601,7 @@ def main():
     ap.add_argument("--creutz-sweeps", type=int, default=100)
     ap.add_argument("--only", default=None,
                     choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped",
-                             "served"],
+                             "batched-resident", "served", "fifo", "small-configs"],
                     help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
@@ -576,9 +627,13 @@ def main():
             leg = run_percolation(b, cpu=False, spanning=False)
         elif args.only == "served":
             leg = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
-        elif args.only in ("batched", "batched-stepped"):
+        elif args.only == "fifo":
+            leg = run_fifo(b, float(args.served_rates.split(",")[0]), args.served_requests)
+        elif args.only == "small-configs":
+            leg = run_small_configs(b, torch, stream)
+        elif args.only.startswith("batched"):
             leg, _ = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0,
-                                 plan=0 if args.only == "batched" else 2)
+                                 plan={"batched": 0, "batched-resident": 1, "batched-stepped": 2}[args.only])
         else:
             leg = run_micro(b, torch, stream)
         print(json.dumps({"leg": args.only, "result": leg}), flush=True)
@@ -589,6 +644,7 @@ def main():
     head = run_headline(b, torch, stream, run, args.steps, args.warmup, tune=not args.no_tune, force=force,
                         first=max(2, args.cpu_sweeps), force_plan=args.plan)
     ms, steps = head["ms"], args.steps
+    progress(f"headline: {run.L * run.L * steps / ms / 1e6:.1f} attempts/ns")
     attempts = run.L * run.L * steps
     value = attempts / ms / 1e6  # attempts per ns
     launch_ms = ms / steps      # one fused launch per sweep (plus one tiny reduce per call)
@@ -604,7 +660,8 @@ def main():
     roof_hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_frac": traffic / HBM_PEAK_GBS if traffic else None, "kernel": kname,
-                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": launch_ms}
+                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": launch_ms,
+                "avg_launch_ms_from": "HIP events on the context's stream around the timed sweeps"}
     roof_alu = None
     if same_kernel:
         ops = prof["valu_lane_ops_per_attempt"] * run.L * run.L / (launch_ms * 1e-3)
@@ -631,9 +688,8 @@ def main():
                    "step": "one full sweep (both colours) with per-sweep B and M",
                    "plan": {"kind": plan_names.get(plan[0], str(plan[0])), "chunk_words": plan[1],
                             "tile_rows": plan[2]}},
-        "roofline": roof_alu if roof_alu else roof_hbm,
-        "roofline_hbm": roof_hbm,
-        "hbm_roof_fraction_at_2B_per_attempt": value / 4000.0,
+        "roofline": roof_hbm,
+        "roofline_alu": roof_alu,
         "host_wall_s": head["host_s"],
     }
 
@@ -641,6 +697,7 @@ def main():
         cpu, parity = cpu_baseline(run, args.cpu_sweeps, head["B0"], head["M0"])
         out["cpu_baseline"] = cpu
         out["parity_first_sweeps_vs_oracle"] = parity
+        progress("cpu baseline")
 
     if not args.no_extra:
         extra = []
@@ -651,32 +708,48 @@ def main():
             extra.append({"h": r.h, "p_up": r.p_up, "sweeps": steps,
                           "value": r.L * r.L * steps / h["ms"] / 1e6, "unit": "attempts/ns"})
         out["c2_other_runs"] = extra
+        progress("other 32768^2 runs")
         # the plan ISING_BATCH_AUTO picks: resident, every lattice of this
         # configuration (h = 0, L <= 1024) held bit-packed in workgroup memory
+        if not args.no_batch_tune:
+            b.ising_batch_tune(0, None, b.ISING_TUNE_RETIME)
         auto, h_au = run_batched(b, torch, stream, 1024, args.batched_sweeps, args.batched_sample, plan=0)
-        auto["plan"] = "auto: resident, lattices bit-packed in workgroup memory"
-        auto["roofline"] = batched_roofline(auto, stepped=False)
-        stepped, h_st = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=2)
-        auto["stepped_plan_same_config"] = {"value": stepped["value"], "ms": stepped["ms"],
-                                            "results_identical": h_st == h_au,
-                                            "roofline": batched_roofline(stepped, stepped=True)}
+        auto["batch_rates_tuned_in_this_run"] = not args.no_batch_tune
+        auto["roofline"] = batched_roofline(auto, stepped=auto["plan"].startswith("stepped"))
+        other = 1 if auto["plan"].startswith("stepped") else 2
+        alt, h_alt = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0, plan=other)
+        auto["other_plan_same_config"] = {"plan": alt["plan"], "value": alt["value"], "ms": alt["ms"],
+                                          "results_identical": h_alt == {k: h_au[k] for k in h_alt},
+                                          "roofline": batched_roofline(alt, stepped=other == 2)}
         out["batched"] = auto
+        progress("batched")
 
     if not args.no_extra and not args.no_served:
         out["served"] = run_served(args.served_rates, args.served_requests, args.epoch_sweeps)
+        progress("served")
         if args.served_subsat_rate > 0:
             sub = run_served(str(args.served_subsat_rate), args.served_requests, args.epoch_sweeps)
             for x in sub:
                 x["label"] = "sub-saturation point (extra, not a configured rate)"
             out["served_subsaturation"] = sub
+        if not args.no_fifo:
+            rates = [float(x) for x in args.served_rates.split(",") if x][:1]
+            if args.served_subsat_rate > 0:
+                rates.append(args.served_subsat_rate)
+            out["served_fifo_comparator"] = [run_fifo(b, r, args.served_requests) for r in rates]
+            progress("served FIFO comparator")
 
     if not args.no_extra:
         out["small_configs"] = run_small_configs(b, torch, stream)
+        progress("small configs")
 
     if not args.no_extra:
         out["creutz"] = run_creutz(b, torch, stream, args.creutz_sweeps, value, cpu=not args.no_cpu)
+        progress("creutz")
         out["percolation"] = run_percolation(b, cpu=not args.no_cpu)
+        progress("percolation")
         out["micro"] = run_micro(b, torch, stream)
+        progress("micro")
 
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")

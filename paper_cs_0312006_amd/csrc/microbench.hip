@@ -25,32 +25,57 @@ __device__ __forceinline__ float apply(float a, float c) {
     return expf(a);
 }
 
-// Grid-stride over float4 (n4 of them), then the scalar tail.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Streaming pass over float4s (n4 of them), then the scalar tail. A block
+// takes chunks of kUnroll * blockDim consecutive float4s (grid-stride over
+// chunks): each thread issues all of its kUnroll loads of a chunk before the
+// first store, and loads and stores are nontemporal (each line is touched
+// once), so many bytes are in flight per wave.
+constexpr int kUnroll = 4;
+
 template <uint32_t OP>
 __global__ void __launch_bounds__(kThreads) k_vec(float* __restrict__ a, const float* __restrict__ c, size_t n) {
     constexpr bool reads_a = OP != MB_OP_COPY;
     constexpr bool reads_c = OP <= MB_OP_DIV;
     const size_t n4 = n / 4;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    float4* a4 = reinterpret_cast<float4*>(a);
-    const float4* c4 = reinterpret_cast<const float4*>(c);
-    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n4; k += stride) {
-        float4 x = reads_a ? a4[k] : float4{0.f, 0.f, 0.f, 0.f};
-        const float4 y = reads_c ? c4[k] : float4{0.f, 0.f, 0.f, 0.f};
-        x.x = apply<OP>(x.x, y.x);
-        x.y = apply<OP>(x.y, y.y);
-        x.z = apply<OP>(x.z, y.z);
-        x.w = apply<OP>(x.w, y.w);
-        a4[k] = x;
+    f32x4* a4 = reinterpret_cast<f32x4*>(a);
+    const f32x4* c4 = reinterpret_cast<const f32x4*>(c);
+    const size_t chunk = (size_t)blockDim.x * kUnroll;
+    for (size_t base = blockIdx.x * chunk; base < n4; base += (size_t)gridDim.x * chunk) {
+        f32x4 x[kUnroll], y[kUnroll];
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const size_t k = base + (size_t)j * blockDim.x + threadIdx.x;
+            x[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            y[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (k < n4) {
+                if (reads_a) x[j] = __builtin_nontemporal_load(a4 + k);
+                if (reads_c) y[j] = __builtin_nontemporal_load(c4 + k);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kUnroll; ++j) {
+            const size_t k = base + (size_t)j * blockDim.x + threadIdx.x;
+            if (k < n4) {
+                f32x4 v;
+                v.x = apply<OP>(x[j].x, y[j].x);
+                v.y = apply<OP>(x[j].y, y[j].y);
+                v.z = apply<OP>(x[j].z, y[j].z);
+                v.w = apply<OP>(x[j].w, y[j].w);
+                __builtin_nontemporal_store(v, a4 + k);
+            }
+        }
     }
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t k = 4 * n4 + blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < n; k += stride)
         a[k] = apply<OP>(reads_a ? a[k] : 0.f, reads_c ? c[k] : 0.f);
 }
 
 template <uint32_t OP>
 hipError_t launch(float* a, const float* c, size_t n, hipStream_t s) {
-    size_t blocks = (n / 4 + kThreads - 1) / kThreads;
-    if (blocks > 8192) blocks = 8192;  // 32 waves per CU, grid-stride beyond
+    size_t blocks = (n / 4 + kThreads * kUnroll - 1) / (kThreads * kUnroll);
+    if (blocks > 2048) blocks = 2048;  // eight workgroups per compute unit, grid-stride beyond
     if (blocks == 0) blocks = 1;
     k_vec<OP><<<(uint32_t)blocks, kThreads, 0, s>>>(a, c, n);
     return hipGetLastError();
