@@ -25,50 +25,44 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit ops)
 
-# Figures measured with rocprofv3 for the fused kernel as built from these
-# sources (profiles/k_fused_ising2d_32768.md), per tile shape. They are
-# reported only while the kernel sources hash to the recorded value and the
-# timed plan is one of these; otherwise they are null. A recorded hash is
-# moved forward after a change elsewhere in these files only once the
-# profiled kernel is seen to compile to the same instructions.
-PROFILED_SOURCES = "f9f355a75190fcc6"
+# Figures measured with rocprofv3 for the kernels as built from these
+# sources (profiles/*.md). Each is keyed by a hash of the kernel's sources
+# and reported only while the tree still hashes to it (otherwise null): a
+# changed kernel is profiled again, never carried forward. HBM bytes are
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch): a 1 GiB device
+# copy in the same runs reads 524300 KiB of FETCH_SIZE and writes 1048576
+# KiB of WRITE_SIZE. VALU lane-ops are SQ_INSTS_VALU x 64; VALU busy is
+# SQ_ACTIVE_INST_VALU / 256 compute units / (GRBM_GUI_ACTIVE / 8 XCDs).
+PROFILED_SOURCES = "5e1d18355bda76c9"
 PROFILED = {
-    # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (KiB per dispatch, mean of 54)
-    "k_fused<4,32>": {"hbm_bytes_per_launch": (690127.8 * 2.0 + 1048863.4) * 1024,
-                      "valu_lane_ops_per_attempt": 256517738.4 * 64 / 2 ** 30,
-                      "valu_busy_rocprof": 0.942},
-    # mean of 52
-    "k_fused<4,16>": {"hbm_bytes_per_launch": (741900.8 * 2.0 + 1049112.3) * 1024,
-                      "valu_lane_ops_per_attempt": 268323794.0 * 64 / 2 ** 30,
-                      "valu_busy_rocprof": 0.990},
+    # profiles/k_fused_rows_ising2d_32768.md, mean of 140 dispatches
+    "k_fused_rows<4,128>": {"hbm_bytes_per_launch": (540867.7 * 2.0 + 1048580.0) * 1024,
+                            "valu_lane_ops_per_attempt": 232145300.4 * 64 / 2 ** 30,
+                            "valu_busy_rocprof": 0.829},
 }
 
 
-# Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md),
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, KiB per dispatch, mean of 22
-PROFILED_CREUTZ_SOURCES = "bfe59632a49acf68"
+# Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md,
+# mean of 22 dispatches)
+PROFILED_CREUTZ_SOURCES = "ab833d4cc0adfdab"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
-                   "hbm_bytes_per_sweep": (1316828.2 * 2.0 + 2097585.8) * 1024}
+                   "hbm_bytes_per_sweep": (1316934.8 * 2.0 + 2097587.6) * 1024}
 
-# Batched configuration (1024 lattices, 10000 sweeps): the bit-packed
-# resident kernel the AUTO plan runs (profiles/k_batch_bits_batched_1024.md,
-# one dispatch of 2000 sweeps) and the stepped plan's fused walk
-# (profiles/k_multi_fused_batched_1024.md, mean per dispatch; FETCH_SIZE x 2.0
-# + WRITE_SIZE x 1.0 KiB)
+# Batched configuration (1024 lattices): the resident kernel the tuned AUTO
+# plan runs (profiles/k_batch_bits_batched_1024.md, one dispatch of 2000
+# sweeps) and the stepped plan's fused walk (profiles/k_multi_fused_batched_1024.md,
+# mean of 160 dispatches, 16-row tiles)
 BATCH_FILES = ("ising_batch.hip", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_BATCH_SOURCES = "30aa04fb478a53b9"
+PROFILED_BATCH_SOURCES = "5437613bc3025381"
 PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
-                  "valu_lane_ops_per_attempt": 192905879841.0 * 64 / (388630784 * 2000),
-                  "valu_busy_rocprof": 0.951}
+                  "valu_lane_ops_per_attempt": 192905902547.0 * 64 / (388630784 * 2000),
+                  "valu_busy_rocprof": 0.928}
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_MULTI_FUSED_SOURCES = "7c1c6aec85944257"
+PROFILED_MULTI_FUSED_SOURCES = "3e199830c7ada852"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
-                        "valu_lane_ops_per_attempt": 123302633.0 * 64 / 388630784,
-                        "valu_busy_rocprof": 0.769,
-                        # share of the tiles' lane slots that hold lattice words
-                        # in this configuration (narrow columns packed)
-                        "lanes_on_lattice_words": 0.766,
-                        "hbm_bytes_per_sweep": (269308.2 * 2.0 + 382538.4) * 1024}
+                        "valu_lane_ops_per_attempt": 131548509.0 * 64 / 388630784,
+                        "valu_busy_rocprof": 0.877,
+                        "hbm_bytes_per_sweep": (287353.4 * 2.0 + 386280.7) * 1024}
 
 
 def batched_roofline(res, stepped):
@@ -88,7 +82,6 @@ def batched_roofline(res, stepped):
         roof["traffic"] = prof["hbm_bytes_per_sweep"] / sweep_s / 1e9
         roof["traffic_unit"] = "GB/s"
         roof["algorithmic_hbm_GBs"] = 2.0 * res["attempts"] / res["sweeps"] / sweep_s / 1e9
-        roof["lanes_on_lattice_words"] = prof["lanes_on_lattice_words"]
     return roof
 
 
