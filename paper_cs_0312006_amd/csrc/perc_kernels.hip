@@ -4,17 +4,18 @@
 // The paper's GPU program spreads the cluster by one pass over the whole
 // lattice per invasion step, so a medium whose cluster needs D steps costs
 // D full passes. Here the arrival pass of every site (its breadth-first
-// distance from the source through pores) is computed directly by
-// relaxation, arrival = min(arrival, 1 + min over the four neighbours), in
-// 64 x 64 tiles held in LDS: a workgroup relaxes its tile to a local fixed
-// point (many steps per HBM round trip), and a tile is revisited only when
-// a neighbouring tile changed the sites on their shared edge. Launch k
-// admits arrival values up to 32 (k + 1) only (larger improvements wait in
-// their tile, which stays queued), so the front is swept roughly in
-// breadth-first order and tiles are seldom recomputed. Values only ever
-// decrease and every read value is an upper bound of the true distance, so
-// the unique fixed point, reached when no tile is queued, is exact
-// whatever the timing of concurrent reads.
+// distance from the source through pores) is computed tile by tile: one
+// wave owns a 64 x 64 tile, lane r holding tile row r as 64 arrival values
+// and as 64-bit masks, and brings the tile to its fixed point (arrival =
+// min(arrival, 1 + min over the four neighbours) for every pore) by
+// breadth-first levels over the masks, a handful of bit operations per row
+// and level; a tile is revisited only when a neighbouring tile changed the
+// sites on their shared edge. Launch k admits arrival values up to 32 (k + 1)
+// only (a tile with sites one level beyond stays queued), so the front is
+// swept roughly in breadth-first order and tiles are seldom revisited.
+// Values only ever decrease and every read value is an upper bound of the
+// true distance, so the unique fixed point, reached when no tile is queued,
+// is exact whatever the timing of concurrent reads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,37 +26,42 @@ namespace perc {
 
 namespace {
 
-constexpr uint32_t kSide = kTile + 2;          // tile plus one-site halo
-constexpr uint32_t kMaxIters = 1u << 14;       // per visit; a tile still changing is queued again
-#ifndef PERC_BOUND_STEP
-#define PERC_BOUND_STEP 32
+constexpr uint32_t kBoundStep = 32;  // arrival passes admitted per launch (32 beat 64, 128 and 256)
+#ifndef PERC_MAX_LEVELS
+#define PERC_MAX_LEVELS 64
 #endif
-constexpr uint32_t kBoundStep = PERC_BOUND_STEP;  // arrival passes admitted per launch
+// Breadth-first levels per tile visit: a launch lasts as long as its
+// longest visit, so a visit that would run longer stops and resumes in the
+// next launch.
+constexpr uint32_t kMaxLevels = PERC_MAX_LEVELS;
 
-// LDS accesses of the relaxation: other waves update neighbouring rows
-// concurrently, so reads and writes are relaxed atomics (plain ds_read /
-// ds_write on the hardware) and may see either value.
-__device__ __forceinline__ uint32_t lds_ld(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+// DPP controls (GFX9): whole-wave shift by one lane.
+constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l+1
+constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l-1
+
+// Row mask of the tile row above (lane l gets lane l-1's; lane 0 gets `edge`)
+// and below (lane l gets lane l+1's; lane 63 gets `edge`).
+__device__ __forceinline__ uint64_t mask_from_above(uint64_t v, uint64_t edge) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)edge, (int)(uint32_t)v, kDppWaveShr1,
+                                                              0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(edge >> 32), (int)(uint32_t)(v >> 32),
+                                                              kDppWaveShr1, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
 }
-__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ uint64_t mask_from_below(uint64_t v, uint64_t edge) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)edge, (int)(uint32_t)v, kDppWaveShl1,
+                                                              0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(edge >> 32), (int)(uint32_t)(v >> 32),
+                                                              kDppWaveShl1, 0xf, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// New arrival of a site from its current value and its four neighbours
-// (solid neighbours hold 0xffffffff, unreached ones kUnreached, and both
-// give kUnreached + 1 > any reachable value). Improvements beyond this
-// launch's bound are left for a later launch and flagged as pending.
-__device__ __forceinline__ uint32_t relax1(uint32_t cur, uint32_t a, uint32_t b, uint32_t c, uint32_t d,
-                                           uint32_t bound, bool& pend) {
-    uint32_t m = min(min(a, b), min(c, d));
-    m = min(m, kUnreached) + 1u;
-    if (m < cur) {
-        if (m <= bound) return m;
-        pend = true;
-    }
-    return cur;
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off, 64));
+    return v;
 }
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
 
 __device__ __forceinline__ void push(const WorkLists& w, uint32_t* queued, uint32_t par, uint32_t lout, uint32_t m,
                                      uint32_t tile) {
@@ -114,142 +120,161 @@ __global__ void __launch_bounds__(kThreads) k_perc_seed(WorkLists w, const Mediu
     }
 }
 
-// One relaxation launch (number k of the run): relax every listed tile to
-// its local fixed point, write back what changed, queue the neighbours
-// whose shared edge changed.
-__global__ void __launch_bounds__(kThreads) k_perc_relax(const Medium* __restrict__ media, WorkLists w, uint32_t pin,
-                                                         uint32_t lin, uint32_t lout, uint32_t lclr, uint32_t bound) {
-    __shared__ uint32_t d[kSide * kSide];
+// One relaxation launch (number k of the run, admitting arrival values up
+// to `bound`, the previous launch's bound being `lo`): a wave per listed
+// tile.
+//
+// A visit takes the tile's halo (the sites just outside its four sides) as
+// sources and computes breadth-first levels from the lowest level d0 at
+// which anything can change: lo, or a halo value h below it that would
+// lower the site next to it (h + 1 less than that site's value). Every
+// stored value is the fixed point of an earlier visit for levels up to lo
+// and halo values only decrease, so below d0 nothing changes and the pores
+// with stored values up to d0 are sources too. From d0, A holds the pores
+// reached by level d; level d + 1 adds the pores next to A or to a halo
+// site of value at most d. A stored value above d0 came from sources no
+// closer than today's, so the levels reach that site at or below it: it is
+// written only where the level is lower. Levels where nothing is added
+// jump to the next halo value. At `bound` the visit stops; a pore that
+// level bound + 1 would reach keeps the tile queued for the next launch.
+__global__ void __launch_bounds__(kRelaxThreads) k_perc_relax(const Medium* __restrict__ media, WorkLists w,
+                                                              uint32_t pin, uint32_t lin, uint32_t lout,
+                                                              uint32_t lclr, uint32_t lo, uint32_t bound) {
+    __shared__ uint32_t vs[kTile][kTile + 1];  // the stored values of the tile being visited
     if (blockIdx.x == 0 && threadIdx.x == 0) w.len[lclr] = 0u;
     const uint32_t n = w.len[lin];
-    const uint32_t x = threadIdx.x & (kTile - 1);
-    const uint32_t y0 = (threadIdx.x / kTile) * kStrip;
-    // row phase: row hr, sites hx0 .. hx0 + 15 (a wave covers 64 rows of
-    // one column segment; the 66-word row pitch spreads them over banks)
-    const uint32_t hr = threadIdx.x & (kTile - 1);
-    const uint32_t hx0 = (threadIdx.x / kTile) * kStrip;
+    const uint32_t r = threadIdx.x;  // the tile row of this lane
     for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
         const uint2 ent = w.list[pin][e];
-        // the entry is the same for the whole workgroup: keep it scalar
+        // the entry is the same for the whole wave: keep it scalar
         const uint32_t m = (uint32_t)__builtin_amdgcn_readfirstlane((int)ent.x);
         const uint32_t tile = (uint32_t)__builtin_amdgcn_readfirstlane((int)ent.y);
         const Medium& md = media[m];
-        uint32_t* const arr = md.arr;
+        ising::global_u32* const arr = ising::as_global(md.arr);
         const uint32_t L = md.L, n_tx = md.n_tx, n_ty = md.n_ty;
         uint32_t* q_in = pin ? md.queued[1] : md.queued[0];
         const uint32_t ty = tile / n_tx, tx = tile - ty * n_tx;
-        const int64_t gi0 = (int64_t)ty * kTile - 1, gj0 = (int64_t)tx * kTile - 1;  // halo origin
-        if (threadIdx.x == 0) q_in[tile] = 0u;
-        for (uint32_t k = threadIdx.x; k < kSide * kSide; k += blockDim.x) {
-            const uint32_t yy = k / kSide, xx = k - yy * kSide;
-            const int64_t gi = gi0 + yy, gj = gj0 + xx;
-            uint32_t v = kSolid;
-            if (gi >= 0 && gj >= 0 && gi < (int64_t)L && gj < (int64_t)L) v = arr[(size_t)gi * L + (size_t)gj];
-            d[k] = v;
+        const uint32_t i0 = ty * kTile, j0 = tx * kTile;
+        if (r == 0) q_in[tile] = 0u;
+        // rows and columns of the tile inside the lattice; every address
+        // below is clamped into the lattice, and a value read for a site
+        // outside it is turned into solid (OR with all ones, so that every
+        // load's result is used and all of them are issued together)
+        const uint32_t nrow = min(kTile, L - i0), ncol = min(kTile, L - j0);
+        const bool row_in = r < nrow, col_in = r < ncol;  // lane r as a row, and as a column
+        const uint32_t gi = i0 + (row_in ? r : nrow - 1);
+        ising::global_u32* const rowp = arr + (size_t)gi * L + j0;
+        const uint32_t out_row = row_in ? 0u : kSolid;
+        uint32_t v[kTile];
+        if (ncol == kTile) {
+#pragma unroll
+            for (uint32_t c = 0; c < kTile; ++c) v[c] = rowp[c] | out_row;
+        } else {
+#pragma unroll
+            for (uint32_t c = 0; c < kTile; ++c) v[c] = rowp[min(c, ncol - 1)] | (c < ncol ? out_row : kSolid);
         }
-        __syncthreads();
-        uint32_t orig[kStrip];
+        // a copy, read where a level reaches a site, to skip values that do
+        // not drop; a padded row per lane keeps the reads free of bank
+        // conflicts
 #pragma unroll
-        for (uint32_t r = 0; r < kStrip; ++r) orig[r] = d[(y0 + r + 1) * kSide + x + 1];
-        uint32_t* col = d + x + 1;  // this thread's column; row yy at col[yy * kSide]
-        uint32_t iters = 0;
-        int go;
-        bool pend;
-        do {
-            bool ch = false;
-            pend = false;
-            {
-                // column strip: LDS rows y0 .. y0 + 17 of column x, own sites
-                // 1 .. 16; all reads issued first, the chain then runs in
-                // registers, top to bottom and back
-                uint32_t c[kStrip + 2], lf[kStrip], rt[kStrip], o[kStrip];
+        for (uint32_t c = 0; c < kTile; ++c) vs[r][c] = v[c];
+        const uint32_t jc = j0 + (col_in ? r : ncol - 1);  // lane r's column, clamped
+        const bool has_top = i0 > 0, has_bot = i0 + kTile < L, has_lft = j0 > 0, has_rgt = j0 + kTile < L;
+        const uint32_t out_col = col_in ? 0u : kSolid;
+        const uint32_t top = arr[(size_t)(has_top ? i0 - 1 : i0) * L + jc] | (has_top ? out_col : kSolid);
+        const uint32_t bot = arr[(size_t)(has_bot ? i0 + kTile : i0) * L + jc] | (has_bot ? out_col : kSolid);
+        const uint32_t first = arr[(size_t)i0 * L + jc];              // tile row 0, column r
+        const uint32_t last = arr[(size_t)(i0 + nrow - 1) * L + jc];  // last tile row, column r
+        const uint32_t lft = rowp[has_lft ? -1 : 0] | (has_lft ? out_row : kSolid);
+        const uint32_t rgt = rowp[has_rgt ? (int)kTile : 0] | (has_rgt ? out_row : kSolid);
+        // the row's pores
+        uint64_t P = 0;
 #pragma unroll
-                for (uint32_t r = 0; r < kStrip + 2; ++r) c[r] = lds_ld(col + (y0 + r) * kSide);
+        for (uint32_t c = 0; c < kTile; ++c) P |= (uint64_t)(v[c] != kSolid) << c;
+        // the lowest level at which the halo lowers a site next to it
+        // (solid and unreached sites are >= kUnreached and lower nothing)
+        uint32_t d0 = lo;
+        if (top < kUnreached && first != kSolid && top + 1u < first) d0 = min(d0, top);
+        if (bot < kUnreached && last != kSolid && bot + 1u < last) d0 = min(d0, bot);
+        if (lft < kUnreached && v[0] != kSolid && lft + 1u < v[0]) d0 = min(d0, lft);
+        if (rgt < kUnreached && v[kTile - 1] != kSolid && rgt + 1u < v[kTile - 1]) d0 = min(d0, rgt);
+        d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32(d0));
+        d0 = min(d0, md.resume[tile]);  // where an earlier visit stopped short
+        uint64_t A = 0, F = 0;  // F: pores with a stored value above d0
 #pragma unroll
-                for (uint32_t r = 0; r < kStrip; ++r) {
-                    lf[r] = lds_ld(col + (y0 + 1 + r) * kSide - 1);
-                    rt[r] = lds_ld(col + (y0 + 1 + r) * kSide + 1);
-                    o[r] = c[r + 1];
-                }
-#pragma unroll
-                for (uint32_t r = 1; r <= kStrip; ++r)
-                    if (c[r] != kSolid) c[r] = relax1(c[r], c[r - 1], c[r + 1], lf[r - 1], rt[r - 1], bound, pend);
-#pragma unroll
-                for (uint32_t r = kStrip; r >= 1; --r)
-                    if (c[r] != kSolid) c[r] = relax1(c[r], c[r - 1], c[r + 1], lf[r - 1], rt[r - 1], bound, pend);
-#pragma unroll
-                for (uint32_t r = 0; r < kStrip; ++r) {
-                    if (c[r + 1] != o[r]) {
-                        lds_st(col + (y0 + 1 + r) * kSide, c[r + 1]);
-                        ch = true;
-                    }
+        for (uint32_t c = 0; c < kTile; ++c) {
+            A |= (uint64_t)(v[c] <= d0) << c;
+            F |= (uint64_t)(v[c] > d0 && v[c] < kUnreached) << c;
+        }
+        // halo sites at or below level d, as tile-row bits
+        auto halo = [&](uint32_t d) {
+            const uint64_t T = __ballot(top <= d), B = __ballot(bot <= d);
+            uint64_t h = (lft <= d ? 1ull : 0ull) | (rgt <= d ? 1ull << (kTile - 1) : 0ull);
+            if (r == 0) h |= T;
+            if (r == nrow - 1) h |= B;
+            return h;
+        };
+        auto grow = [&](uint64_t a, uint32_t d) {
+            return a | (a << 1) | (a >> 1) | mask_from_above(a, 0) | mask_from_below(a, 0) | halo(d);
+        };
+        uint64_t W = 0;
+        uint32_t levels = 0;
+        const uint32_t stop = bound - d0 > kMaxLevels ? d0 + kMaxLevels : bound;
+        uint32_t d = d0;
+        while (d < stop) {
+            const uint64_t nw = grow(A, d) & P & ~A;
+            uint64_t x = nw & ~F;  // unreached until now: always written
+            W |= x;
+            while (x) {
+                const uint32_t c = (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                rowp[c] = d + 1u;
+            }
+            x = nw & F;
+            while (x) {
+                const uint32_t c = (uint32_t)__builtin_ctzll(x);
+                x &= x - 1;
+                if (vs[r][c] > d + 1u) {
+                    rowp[c] = d + 1u;
+                    W |= 1ull << c;
                 }
             }
-            // each site has one writer per phase: its column owner above,
-            // its row owner below, so a site's value never goes up
-            __syncthreads();
-            {
-                // row segment: LDS columns hx0 .. hx0 + 17 of row hr + 1, own
-                // sites 1 .. 16, left to right and back
-                uint32_t* row = d + (hr + 1) * kSide + hx0;
-                uint32_t c[kStrip + 2], up[kStrip], dn[kStrip], o[kStrip];
-#pragma unroll
-                for (uint32_t k = 0; k < kStrip + 2; ++k) c[k] = lds_ld(row + k);
-#pragma unroll
-                for (uint32_t k = 0; k < kStrip; ++k) {
-                    up[k] = lds_ld(row + k + 1 - kSide);
-                    dn[k] = lds_ld(row + k + 1 + kSide);
-                    o[k] = c[k + 1];
-                }
-#pragma unroll
-                for (uint32_t k = 1; k <= kStrip; ++k)
-                    if (c[k] != kSolid) c[k] = relax1(c[k], c[k - 1], c[k + 1], up[k - 1], dn[k - 1], bound, pend);
-#pragma unroll
-                for (uint32_t k = kStrip; k >= 1; --k)
-                    if (c[k] != kSolid) c[k] = relax1(c[k], c[k - 1], c[k + 1], up[k - 1], dn[k - 1], bound, pend);
-#pragma unroll
-                for (uint32_t k = 0; k < kStrip; ++k) {
-                    if (c[k + 1] != o[k]) {
-                        lds_st(row + k + 1, c[k + 1]);
-                        ch = true;
-                    }
-                }
+            A |= nw;
+            ++levels;
+            ++d;
+            if (!wave_any(nw != 0)) {
+                // nothing added: the next level that can add a site is a
+                // halo value at or above d
+                uint32_t nx = bound;
+                nx = min(nx, top >= d ? top : kSolid);
+                nx = min(nx, bot >= d ? bot : kSolid);
+                nx = min(nx, lft >= d ? lft : kSolid);
+                nx = min(nx, rgt >= d ? rgt : kSolid);
+                d = (uint32_t)__builtin_amdgcn_readfirstlane((int)wave_min_u32(nx));
             }
-            ++iters;
-            go = __syncthreads_or(ch);
-        } while (go && iters < kMaxIters);
-        // pending improvements of the last (unchanging) iteration: revisit
-        // the tile in the next launch, whose bound is higher
-        const int later = __syncthreads_or(pend);
-        if (threadIdx.x == 0) {
+        }
+        // stopped short of bound: the values are the fixed point up to d,
+        // and the tile's next visit starts there; otherwise, pores that
+        // level bound + 1 would reach keep the tile queued
+        const bool short_stop = d < bound;
+        if (r == 0 && (short_stop || md.resume[tile] != kSolid)) md.resume[tile] = short_stop ? d : kSolid;
+        const bool later = short_stop || wave_any((grow(A, bound) & P & ~A) != 0);
+        if (r == 0) {
             atomicAdd(&md.stats->visits, 1ull);
-            atomicAdd(&md.stats->iterations, (unsigned long long)iters);
+            atomicAdd(&md.stats->iterations, (unsigned long long)levels);
         }
-        bool top = false, bot = false, lft = false, rgt = false;
-#pragma unroll
-        for (uint32_t r = 0; r < kStrip; ++r) {
-            const uint32_t v = d[(y0 + r + 1) * kSide + x + 1];
-            if (v != orig[r]) {
-                // sites beyond the lattice are solid and never change
-                arr[(size_t)(gi0 + 1 + y0 + r) * L + (size_t)(gj0 + 1 + x)] = v;
-                top |= (y0 + r) == 0u;
-                bot |= (y0 + r) == kTile - 1;
-                lft |= x == 0u;
-                rgt |= x == kTile - 1;
-            }
-        }
-        top = __syncthreads_or(top);
-        bot = __syncthreads_or(bot);
-        lft = __syncthreads_or(lft);
-        rgt = __syncthreads_or(rgt);
-        if (threadIdx.x == 0) {
+        const bool top_ch = wave_any(r == 0 && W != 0);
+        const bool bot_ch = wave_any(r == kTile - 1 && W != 0);
+        const bool lft_ch = wave_any((W & 1u) != 0);
+        const bool rgt_ch = wave_any(((W >> (kTile - 1)) & 1u) != 0);
+        if (r == 0) {
             const uint32_t par = pin ^ 1u;
             uint32_t* q_out = par ? md.queued[1] : md.queued[0];
-            if (top && ty > 0) push(w, q_out, par, lout, m, tile - n_tx);
-            if (bot && ty + 1 < n_ty) push(w, q_out, par, lout, m, tile + n_tx);
-            if (lft && tx > 0) push(w, q_out, par, lout, m, tile - 1);
-            if (rgt && tx + 1 < n_tx) push(w, q_out, par, lout, m, tile + 1);
-            if (go || later) push(w, q_out, par, lout, m, tile);  // not yet at its fixed point
+            if (top_ch && ty > 0) push(w, q_out, par, lout, m, tile - n_tx);
+            if (bot_ch && ty + 1 < n_ty) push(w, q_out, par, lout, m, tile + n_tx);
+            if (lft_ch && tx > 0) push(w, q_out, par, lout, m, tile - 1);
+            if (rgt_ch && tx + 1 < n_tx) push(w, q_out, par, lout, m, tile + 1);
+            if (later) push(w, q_out, par, lout, m, tile);
         }
     }
 }
@@ -310,10 +335,10 @@ hipError_t launch_relax(const Medium* media, const WorkLists& w, uint64_t k, uin
     // arrival passes accepted in launch k: up to (k + 1) * kBoundStep, so the
     // invasion front is swept in order, a band per launch, and tiles are
     // rarely revisited with a better value
-    const uint64_t b = (k + 1) * (uint64_t)kBoundStep;
-    const uint32_t bound = b >= kUnreached ? kUnreached - 1 : (uint32_t)b;
-    k_perc_relax<<<grid, kThreads, 0, s>>>(media, w, (uint32_t)(k % 2), (uint32_t)(k % 3), (uint32_t)((k + 1) % 3),
-                                           (uint32_t)((k + 2) % 3), bound);
+    auto cap = [](uint64_t b) { return b >= kUnreached ? kUnreached - 1 : (uint32_t)b; };
+    const uint32_t bound = cap((k + 1) * (uint64_t)kBoundStep), lo = cap(k * (uint64_t)kBoundStep);
+    k_perc_relax<<<grid, kRelaxThreads, 0, s>>>(media, w, (uint32_t)(k % 2), (uint32_t)(k % 3),
+                                                (uint32_t)((k + 1) % 3), (uint32_t)((k + 2) % 3), lo, bound);
     return hipGetLastError();
 }
 

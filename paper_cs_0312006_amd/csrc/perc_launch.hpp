@@ -8,8 +8,8 @@
 namespace perc {
 
 constexpr uint32_t kTile = 64;               // tile side (sites)
-constexpr uint32_t kThreads = 256;           // per workgroup: a 64-wide column of 16-site strips
-constexpr uint32_t kStrip = kTile * kTile / kThreads;
+constexpr uint32_t kThreads = 256;           // per workgroup of the draw, seed and finish passes
+constexpr uint32_t kRelaxThreads = kTile;    // relaxation: one wave per tile, a lane per tile row
 constexpr uint32_t kSolid = 0xffffffffu;     // arrival of a solid site (-1 as int32)
 constexpr uint32_t kUnreached = 0x7fffffffu; // pore not (yet) invaded
 
@@ -19,13 +19,14 @@ struct Stats {
     uint32_t max_arrival;
     uint32_t edges;  // bit 0 row 0, bit 1 row L-1, bit 2 column 0, bit 3 column L-1
     unsigned long long visits;      // tile visits over all relaxation launches
-    unsigned long long iterations;  // relaxation iterations summed over visits
+    unsigned long long iterations;  // breadth-first levels summed over visits
 };
 
 // One medium of a run (a run relaxes one or several media together).
 struct Medium {
     uint32_t* arr;        // arrival passes, row-major
     uint32_t* queued[2];  // per tile: is it in work list 0 / 1
+    uint32_t* resume;     // per tile: level from which its next visit must start (all ones: none)
     Stats* stats;
     uint32_t L, n_tx, n_ty, pad;
 };

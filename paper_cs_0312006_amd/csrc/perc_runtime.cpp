@@ -24,6 +24,7 @@ struct perc_ctx {
     uint8_t* pore = nullptr;
     uint32_t* arr = nullptr;
     uint32_t* queued[2] = {nullptr, nullptr};
+    uint32_t* resume = nullptr;
     Stats* stats = nullptr;
     Medium md{};              // this medium's descriptor (host copy)
     Medium* d_md = nullptr;   // ... and on the device, for runs of this medium alone
@@ -90,7 +91,7 @@ uint32_t relax_grid(uint64_t tiles, int device) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-    return (uint32_t)std::min<uint64_t>(tiles, (uint64_t)cus * 8u);
+    return (uint32_t)std::min<uint64_t>(tiles, (uint64_t)cus * 16u);  // one-wave workgroups
 }
 
 // Draw and invade the media ctxs[0..count) on stream s, with work lists w
@@ -108,6 +109,7 @@ int run_media(perc_ctx* const* ctxs, size_t count, hipStream_t s, const WorkList
         PERC_TRY(c0, hipMemsetAsync(c->stats, 0, sizeof(Stats), s));
         PERC_TRY(c0, hipMemsetAsync(c->queued[0], 0, (size_t)c->n_tiles * 4, s));
         PERC_TRY(c0, hipMemsetAsync(c->queued[1], 0, (size_t)c->n_tiles * 4, s));
+        PERC_TRY(c0, hipMemsetAsync(c->resume, 0xff, (size_t)c->n_tiles * 4, s));
         PERC_TRY(c0, launch_draw(c->pore, c->arr, p.L, pthr, (uint32_t)p.seed, (uint32_t)(p.seed >> 32), p.source,
                                  p.i0, p.j0, c->stats, s));
     }
@@ -166,6 +168,7 @@ int perc_create(const perc_params* params, void* stream, perc_ctx** out) {
     c->grid = relax_grid(c->n_tiles, c->device);
     bool ok = dev_alloc(&c->pore, c->N) && dev_alloc(&c->arr, c->N * sizeof(uint32_t)) &&
               dev_alloc(&c->queued[0], (size_t)c->n_tiles * 4) && dev_alloc(&c->queued[1], (size_t)c->n_tiles * 4) &&
+              dev_alloc(&c->resume, (size_t)c->n_tiles * 4) &&
               dev_alloc(&c->stats, sizeof(Stats)) && dev_alloc(&c->d_md, sizeof(Medium)) &&
               dev_alloc(&c->w.list[0], (size_t)c->n_tiles * sizeof(uint2)) &&
               dev_alloc(&c->w.list[1], (size_t)c->n_tiles * sizeof(uint2)) &&
@@ -176,7 +179,7 @@ int perc_create(const perc_params* params, void* stream, perc_ctx** out) {
         ok = false;
     }
     if (ok) {
-        c->md = Medium{c->arr, {c->queued[0], c->queued[1]}, c->stats, L, c->n_tx, c->n_ty, 0u};
+        c->md = Medium{c->arr, {c->queued[0], c->queued[1]}, c->resume, c->stats, L, c->n_tx, c->n_ty, 0u};
         ok = hipMemcpy(c->d_md, &c->md, sizeof(Medium), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
@@ -305,6 +308,7 @@ int perc_destroy(perc_ctx* c) {
         (void)hipFree(c->w.list[k]);
         (void)hipFree(c->queued[k]);
     }
+    (void)hipFree(c->resume);
     (void)hipFree(c->w.len);
     (void)hipFree(c->stats);
     (void)hipFree(c->d_md);
