@@ -165,26 +165,24 @@ __global__ void __launch_bounds__(kRelaxThreads) k_perc_relax(const Medium* __re
         const uint32_t gi = i0 + (row_in ? r : nrow - 1);
         ising::global_u32* const rowp = arr + (size_t)gi * L + j0;
         const uint32_t out_row = row_in ? 0u : kSolid;
-        uint32_t v[kTile];
-        if (ncol == kTile) {
-#pragma unroll
-            for (uint32_t c = 0; c < kTile; ++c) v[c] = rowp[c] | out_row;
-        } else {
-#pragma unroll
-            for (uint32_t c = 0; c < kTile; ++c) v[c] = rowp[min(c, ncol - 1)] | (c < ncol ? out_row : kSolid);
-        }
-        // a copy, read where a level reaches a site, to skip values that do
-        // not drop; a padded row per lane keeps the reads free of bank
-        // conflicts
-#pragma unroll
-        for (uint32_t c = 0; c < kTile; ++c) vs[r][c] = v[c];
+        // the tile's stored values into LDS row by row, lane r taking
+        // column r (each load reads 64 consecutive words), then each lane's
+        // row back out of LDS; the padded row keeps both directions free of
+        // bank conflicts. The copy stays for the levels, which read it where
+        // a site is reached, to skip values that do not drop.
         const uint32_t jc = j0 + (col_in ? r : ncol - 1);  // lane r's column, clamped
-        const bool has_top = i0 > 0, has_bot = i0 + kTile < L, has_lft = j0 > 0, has_rgt = j0 + kTile < L;
         const uint32_t out_col = col_in ? 0u : kSolid;
+#pragma unroll 16
+        for (uint32_t rr = 0; rr < kTile; ++rr)
+            vs[rr][r] = arr[(size_t)(i0 + min(rr, nrow - 1)) * L + jc] | (rr < nrow ? out_col : kSolid);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t v[kTile];
+#pragma unroll
+        for (uint32_t c = 0; c < kTile; ++c) v[c] = vs[r][c];
+        const bool has_top = i0 > 0, has_bot = i0 + kTile < L, has_lft = j0 > 0, has_rgt = j0 + kTile < L;
         const uint32_t top = arr[(size_t)(has_top ? i0 - 1 : i0) * L + jc] | (has_top ? out_col : kSolid);
         const uint32_t bot = arr[(size_t)(has_bot ? i0 + kTile : i0) * L + jc] | (has_bot ? out_col : kSolid);
-        const uint32_t first = arr[(size_t)i0 * L + jc];              // tile row 0, column r
-        const uint32_t last = arr[(size_t)(i0 + nrow - 1) * L + jc];  // last tile row, column r
+        const uint32_t first = vs[0][r], last = vs[nrow - 1][r];  // tile row 0 and the last, column r
         const uint32_t lft = rowp[has_lft ? -1 : 0] | (has_lft ? out_row : kSolid);
         const uint32_t rgt = rowp[has_rgt ? (int)kTile : 0] | (has_rgt ? out_row : kSolid);
         // the row's pores
