@@ -434,7 +434,7 @@ def run_percolation(b, cpu=True, spanning=True):
                     "ms": s * 1e3, "value": N / s / 1e9, "unit": "medium sites/ns (draw + invasion to steady state)",
                     "passes_to_steady_state": r.passes, "invaded": r.invaded, "spans": r.spans,
                     "relax_launches": r.launches, "tile_visits": r.tile_visits,
-                    "relax_iterations_per_visit": r.tile_iterations / max(1, r.tile_visits),
+                    "levels_per_visit": r.tile_iterations / max(1, r.tile_visits),
                     "paper_method_equivalent": {
                         "value": N * max(1, r.passes) / s / 1e9,
                         "unit": "site-passes/ns (one full pass per invasion step, as in Section 2.3)"}})

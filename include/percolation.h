@@ -51,7 +51,7 @@ typedef struct perc_result {
     uint32_t launches;         /* relaxation launches */
     uint32_t pad;
     uint64_t tile_visits;      /* 64 x 64 tiles relaxed, summed over launches */
-    uint64_t tile_iterations;  /* relaxation iterations, summed over tile visits */
+    uint64_t tile_iterations;  /* breadth-first levels run, summed over tile visits */
     uint64_t arrival_hash;  /* FNV-1a-64 of the int32 arrival map, little-endian row-major (opt-in) */
 } perc_result;
 
