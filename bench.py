@@ -153,6 +153,17 @@ def run_headline(b, torch, stream, run, steps, warmup, tune=True, force=None, fi
     return {"ms": ms, "host_s": host_s, "plan": plan, "B0": B0, "M0": M0, "B": B, "M": M, "obs": obs}
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(run, sweeps, B0, M0):
     """The oracle (plain C, OpenMP over rows) on the host cores: initial
     state plus `sweeps` sweeps of the same lattice; its series must equal
@@ -173,6 +184,7 @@ def cpu_baseline(run, sweeps, B0, M0):
         "value": attempts / (t2 - t1) / 1e9,
         "unit": "spin-update attempts/ns",
         "cores": cores,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": f"{sweeps} sweeps of the {run.L}x{run.L} lattice from its initial state "
                   f"(init {t1 - t0:.1f} s not counted); series equal to the GPU's: {parity}",
@@ -714,6 +726,7 @@ def main():
         auto["other_plan_same_config"] = {"plan": alt["plan"], "value": alt["value"], "ms": alt["ms"],
                                           "results_identical": h_alt == {k: h_au[k] for k in h_alt},
                                           "roofline": batched_roofline(alt, stepped=other == 2)}
+        auto["hbm_roof_fraction_at_2B_per_attempt"] = auto["value"] / (HBM_PEAK_GBS / 2.0)
         out["batched"] = auto
         progress("batched")
 
@@ -743,6 +756,12 @@ def main():
         progress("percolation")
         out["micro"] = run_micro(b, torch, stream)
         progress("micro")
+        # the headline against what this part measurably streams, and against
+        # the rate its Philox draws alone would allow
+        copy_gbs = out["micro"]["achievable_hbm_copy_GB_per_s"]
+        out["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
+        draws_only = out["micro"]["philox"]["site_updates_per_ns_if_only_draws"]
+        out["frac_of_philox_only_rate"] = value / draws_only
 
     if args.calibrate_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
