@@ -73,6 +73,10 @@ extern "C" {
 #define ISING_PLAN_RESIDENT 3u  /* one workgroup runs all sweeps of the call */
 #define ISING_PLAN_GENERIC 4u   /* per-site draws; the only path for L % 8 != 0 */
 #define ISING_PLAN_FUSED_ROWS 5u /* as FUSED, a workgroup per band of whole rows (L/8 <= 16 * 64 * cw) */
+#define ISING_PLAN_BANDS 6u      /* the lattice split into bands of whole rows, one workgroup each, all
+                                   * resident at once; each band stays in LDS at one bit per site for
+                                   * every sweep of a call, bands trade edge rows after each half-sweep
+                                   * (L % 8 == 0, L <= 4096) */
 
 /* Model and run parameters (Section 2.2: L x L lattice, coupling J, field h,
  * temperature T, spin-up probability p_up of the initial state). */
@@ -156,8 +160,10 @@ int ising_sweep(ising_ctx* ctx, uint64_t n);
  * its last contents there (the kernels write each slot before they read
  * it): calls that overlap on one device, on any streams, race and must be
  * ordered by the caller. The fused plan needs 2 x its tiles pairs (32768^2
- * with 32-row tiles: 32768), the two-pass plan one per block; the resident
- * and per-site plans need none. Errors: EINVAL (NULL ctx or series_dev),
+ * with 32-row tiles: 32768), the two-pass plan one per block, the band
+ * plan one per band and sweep (its launches are split so that they fit; its
+ * edge-row slots and flags were allocated when the plan was set); the
+ * resident and per-site plans need none. Errors: EINVAL (NULL ctx or series_dev),
  * ERANGE (t + n > 2^32, or the plan needs more pairs than the array holds:
  * pick taller tiles with ising_plan_set), ESTATE, EDEVICE. */
 #define ISING_STATIC_SCRATCH_PAIRS 65536u
@@ -302,8 +308,12 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
 /* Force the plan of a context (ISING_PLAN_*; for ISING_PLAN_FUSED also the
  * chunk width cw in {1, 2, 4} words per lane and the tile height rows in
  * {4, 8, 16, 32, 64, 128}; for ISING_PLAN_FUSED_ROWS cw and the band height
- * rows in {8, 16, 32, 64, 128}, with L/8 / (64 cw) <= 16; 0 picks a default). Switching to the fused plan may
- * allocate a second lattice buffer. Results do not depend on the plan.
+ * rows in {8, 16, 32, 64, 128}, with L/8 / (64 cw) <= 16; for
+ * ISING_PLAN_BANDS the band height rows >= 1, giving ceil(L / rows) >= 2
+ * bands that must all fit the device at once, cw ignored; 0 picks a
+ * default). Switching to the fused plan may allocate a second lattice
+ * buffer, to the band plan its edge-row slots and flags. Results do not
+ * depend on the plan.
  * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
 

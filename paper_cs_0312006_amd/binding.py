@@ -31,6 +31,7 @@ ISING_PLAN_FUSED = 2
 ISING_PLAN_RESIDENT = 3
 ISING_PLAN_GENERIC = 4
 ISING_PLAN_FUSED_ROWS = 5
+ISING_PLAN_BANDS = 6
 
 ISING_BATCH_AUTO = 0
 ISING_BATCH_RESIDENT = 1

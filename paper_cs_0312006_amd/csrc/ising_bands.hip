@@ -1,0 +1,258 @@
+// Band-resident sweeps of one lattice too large for a workgroup's LDS but
+// small enough for the LDS of the whole chip (Section 2.2's consecutive
+// black and white passes, every one of them kept on chip).
+//
+// The L rows are split into G bands, band g holding rows [g L / G,
+// (g + 1) L / G), one workgroup per band, all resident at once (a
+// cooperative launch). A workgroup converts its band of both colour planes
+// to bits in LDS (the layout and word update of ising_bits.hpp), runs every
+// half-sweep of the launch there and converts the band back at the end, so
+// the lattice crosses HBM once per launch rather than once per sweep.
+//
+// A band's first and last rows need the rows just outside it, which belong
+// to the bands above and below. After each half-sweep the wave that updated
+// a band's first (last) row stores each of its words to an edge slot in
+// global memory as one 64-bit agent-scope atomic holding the word and a tag,
+// the number of the half-sweep (counted across launches from `base`); before
+// a half-sweep the wave that updates a first (last) row reads the upper
+// (lower) band's slot until every word carries the previous half-sweep's
+// tag. A word and its tag travel in one atomic, so no fence orders them:
+// the slots are the only memory bands share during a launch, and agent-scope
+// atomics reach every XCD without writing back or invalidating the L2 (the
+// fences an agent-scope flag would need cost about 40 ns per workgroup,
+// serialised over the chip). Only these two waves of a workgroup wait on
+// another workgroup; the rest wait only at the workgroup barrier that ends
+// each half-sweep. Edge slots alternate between two buffers by half-sweep
+// parity: a band cannot publish half-sweep tau + 1 over the slot of tau - 1
+// before its neighbour has published tau, which that neighbour does only
+// after reading tau - 1.
+// The lattice is updated in place: a band's rows in HBM are read by its
+// neighbours at their first half-sweep and written back only after the
+// band's last one, which waits on both neighbours' second to last.
+//
+// Tags grow across launches, so slots are cleared only when the 32-bit tag
+// would wrap. Every wait gives up after a bounded number of polls, marks
+// *err and lets every later wait of the launch fall through, so a launch
+// always ends.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "ising_bands.hpp"
+#include "ising_bits.hpp"
+#include "ising_launch.hpp"
+
+namespace ising {
+
+namespace {
+
+constexpr uint32_t kBandMaxWaves = 16;
+// Polls of an edge word (each followed by a short sleep) before a wait gives up:
+// about a second.
+constexpr uint32_t kBandMaxPolls = 1u << 24;
+
+__device__ __forceinline__ void put_word(uint64_t* p, uint32_t tag, uint32_t w) {
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The word at p once its tag is `tag` (the whole wave waits until every
+// lane's word has it).
+__device__ __forceinline__ uint32_t take_word(const uint64_t* p, uint32_t tag, uint32_t* err) {
+    uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t polls = 0;
+    while (__ballot((uint32_t)(v >> 32) != tag)) {
+        if ((++polls & 255u) == 0u) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            if (polls >= kBandMaxPolls) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return (uint32_t)v;
+}
+
+// Bit word k of row i of a byte plane (bit 4 j + b is byte b of quad 8 k + j).
+__device__ __forceinline__ uint32_t bits_of_bytes(const uint32_t* plane, uint32_t i, uint32_t k, uint32_t Hw) {
+    const uint32_t* q = plane + (size_t)i * Hw + 8u * k;
+    uint32_t v = 0;
+    for (uint32_t j = 0; j < 8u && 8u * k + j < Hw; ++j) v |= ((q[j] * 0x01020408u) >> 24) << (4u * j);
+    return v;
+}
+
+__device__ __forceinline__ void bytes_of_bits(uint32_t* plane, uint32_t i, uint32_t k, uint32_t Hw, uint32_t v) {
+    uint32_t* q = plane + (size_t)i * Hw + 8u * k;
+    for (uint32_t j = 0; j < 8u && 8u * k + j < Hw; ++j) q[j] = (((v >> (4u * j)) & 0xfu) * 0x00204081u) & 0x01010101u;
+}
+
+template <bool GENERAL>
+__global__ __launch_bounds__(1024) void k_bands(BandArgs a) {
+    extern __shared__ uint32_t lat[];  // [plane][band row][Wr]
+    __shared__ uint32_t red[kBandMaxWaves][2];
+    const BitsLattice& bl = a.bl;
+    const uint32_t G = gridDim.x, g = blockIdx.x;
+    const uint32_t L = a.L, Hw = a.Hw, Wr = a.Wr;
+    const uint32_t r0 = (uint32_t)((uint64_t)g * L / G);
+    const uint32_t H = (uint32_t)((uint64_t)(g + 1u) * L / G) - r0;
+    const uint32_t P = H * Wr;
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t gu = g == 0 ? G - 1u : g - 1u, gd = g + 1u == G ? 0u : g + 1u;
+
+    for (uint32_t w = threadIdx.x; w < 2u * P; w += blockDim.x) {
+        const uint32_t c = w >= P ? 1u : 0u, rw = w - c * P, r = rw / Wr;
+        lat[w] = bits_of_bytes(c ? a.p1 : a.p0, r0 + r, rw - r * Wr, Hw);
+    }
+    __syncthreads();
+
+    const uint32_t k = lane;
+    const bool active = k < Wr;
+    const bool lastw = k + 1u == Wr;
+    const uint32_t valid = lastw ? bl.last_valid : 0xffffffffu;
+    const uint32_t top = lastw ? bl.hb : 31u;
+    const uint32_t kn = lastw ? 0u : k + 1u, kp = k == 0 ? Wr - 1u : k - 1u;
+    const uint32_t top_p = k == 0 ? bl.hb : 31u;
+    // rows of this wave: r = wv (mod nw), the band's edge rows first
+    const uint32_t nrows = H > wv ? (H - 1u - wv) / nw + 1u : 0u;
+    const bool owns_last = (H - 1u) % nw == wv;
+    const size_t slot_words = (size_t)G * 2u * Wr;
+    const uint32_t summer = nw > 1u ? 64u : 0u;  // a thread off the first wave's edge row
+    uint32_t mis = 0, ups = 0;
+
+    for (uint32_t tau = 0; tau < 2u * a.n; ++tau) {
+        const uint32_t c = tau & 1u, t = a.t0 + (tau >> 1);
+        uint32_t* own_p = lat + c * P;
+        const uint32_t* oth_p = lat + (1u - c) * P;
+        const uint32_t* oth_g = c ? a.p0 : a.p1;  // the other plane in HBM (first half-sweep)
+        const uint64_t* in_slot = a.pub + (size_t)((tau - 1u) & 1u) * slot_words;
+        uint64_t* out_slot = a.pub + (size_t)(tau & 1u) * slot_words;
+        const uint32_t tag_in = a.base + tau, tag_out = a.base + tau + 1u;
+        const uint32_t kc = active ? k : Wr - 1u;  // lanes past the row poll its last word
+        for (uint32_t j = 0; j < nrows; ++j) {
+            uint32_t r;
+            if (owns_last && wv != 0u) r = j == 0 ? H - 1u : wv + (j - 1u) * nw;
+            else if (owns_last && H > 1u) r = j == 0 ? 0u : j == 1u ? H - 1u : (j - 1u) * nw;
+            else r = wv + j * nw;
+            const uint32_t i = r0 + r;
+            uint32_t U = 0, D = 0;
+            if (r == 0) {
+                if (tau == 0) {
+                    if (active) U = bits_of_bytes(oth_g, i == 0 ? L - 1u : i - 1u, k, Hw);
+                } else {
+                    U = take_word(in_slot + (2u * gu + 1u) * Wr + kc, tag_in, a.err);
+                }
+            } else if (active) {
+                U = oth_p[(r - 1u) * Wr + k];
+            }
+            if (r == H - 1u) {
+                if (tau == 0) {
+                    if (active) D = bits_of_bytes(oth_g, i + 1u == L ? 0u : i + 1u, k, Hw);
+                } else {
+                    D = take_word(in_slot + 2u * gd * Wr + kc, tag_in, a.err);
+                }
+            } else if (active) {
+                D = oth_p[(r + 1u) * Wr + k];
+            }
+            if (active) {
+                const uint32_t own = own_p[r * Wr + k];
+                const uint32_t O = oth_p[r * Wr + k], On = oth_p[r * Wr + kn], Op = oth_p[r * Wr + kp];
+                const uint32_t S = bits_same_row(O, On, Op, top, top_p, valid, (i + c) & 1u);
+                const uint32_t reject = bits_reject<GENERAL>(bl, own, U, D, O, S, i * Hw + 8u * k, t, c, a.k0, a.k1);
+                const uint32_t nwd = own ^ (valid & ~reject);
+                own_p[r * Wr + k] = nwd;
+                if (r == 0) put_word(out_slot + 2u * g * Wr + k, tag_out, nwd);
+                if (r == H - 1u) put_word(out_slot + (2u * g + 1u) * Wr + k, tag_out, nwd);
+                if (c) {
+                    // bonds of this colour-1 word, all final now, that disagree
+                    mis += __builtin_popcount(nwd ^ U) + __builtin_popcount(nwd ^ D) +
+                           __builtin_popcount(nwd ^ O) + __builtin_popcount(nwd ^ S);
+                }
+                ups += __builtin_popcount(nwd);
+            }
+        }
+        if (c) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                mis += __shfl_xor(mis, off, 64);
+                ups += __shfl_xor(ups, off, 64);
+            }
+            if (lane == 0) {
+                red[wv][0] = mis;
+                red[wv][1] = ups;
+            }
+            mis = 0;
+            ups = 0;
+        }
+        __syncthreads();
+        if (c && threadIdx.x == summer) {
+            int64_t sm = 0, su = 0;
+            for (uint32_t w = 0; w < nw; ++w) {
+                sm += red[w][0];
+                su += red[w][1];
+            }
+            // the band's colour-1 sites own 2 H L bonds, each counted once
+            const int64_t HL = (int64_t)H * L;
+            int64_t* p = a.part + 2u * ((size_t)(tau >> 1) * G + g);
+            p[0] = 2 * HL - 2 * sm;
+            p[1] = 2 * su - HL;
+        }
+    }
+
+    for (uint32_t w = threadIdx.x; w < 2u * P; w += blockDim.x) {
+        const uint32_t c = w >= P ? 1u : 0u, rw = w - c * P, r = rw / Wr;
+        bytes_of_bits(c ? a.p1 : a.p0, r0 + r, rw - r * Wr, Hw, lat[w]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bands_clear(uint64_t* pub, size_t words) {
+    for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (size_t)gridDim.x * blockDim.x)
+        pub[w] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_bands_reduce(const int64_t* part, uint32_t G, int64_t* ser) {
+    const uint32_t s = blockIdx.x;
+    reduce_partials(PartialReduce{part + 2ull * s * G, G, ser + 2ull * s});
+}
+
+const void* bands_kernel(bool general) {
+    return general ? reinterpret_cast<const void*>(&k_bands<true>) : reinterpret_cast<const void*>(&k_bands<false>);
+}
+
+}  // namespace
+
+uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bands_kernel(general), (int)threads, lds_bytes) !=
+        hipSuccess)
+        return 0;
+    return (uint32_t)(per > 0 ? per : 0) * (uint32_t)cus;
+}
+
+hipError_t launch_bands(const BandArgs& a, uint32_t G, uint32_t threads, hipStream_t s) {
+    if (G < 2u || G > a.L || a.Wr == 0 || a.Wr > kBandMaxWr || a.n == 0 || threads % 64u != 0 || threads == 0 ||
+        threads > 64u * kBandMaxWaves)
+        return hipErrorInvalidValue;
+    BandArgs arg = a;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(bands_kernel(a.general != 0), dim3(G), dim3(threads), args,
+                                      band_lds_bytes(a.L, G, a.Wr), s);
+}
+
+hipError_t launch_bands_clear(uint64_t* pub, size_t words, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_bands_clear, dim3((uint32_t)blocks), dim3(256), 0, s, pub, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_bands_reduce(const int64_t* part, uint32_t G, uint32_t n, int64_t* ser, hipStream_t s) {
+    if (n == 0 || G == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bands_reduce, dim3(n), dim3(256), 0, s, part, G, ser);
+    return hipGetLastError();
+}
+
+}  // namespace ising

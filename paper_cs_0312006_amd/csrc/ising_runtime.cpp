@@ -66,7 +66,7 @@ static bool valid_params(const ising_params* p) {
     if (p->L < 2 || (p->L & 1u) || p->L > ISING_MAX_L) return false;
     if (!std::isfinite(p->J) || !std::isfinite(p->h) || !std::isfinite(p->T) || !(p->T > 0.0)) return false;
     if (!(p->p_up >= 0.0 && p->p_up <= 1.0)) return false;
-    if ((p->flags & 0xffu) > ISING_PLAN_FUSED_ROWS) return false;
+    if ((p->flags & 0xffu) > ISING_PLAN_BANDS) return false;
     return true;
 }
 
@@ -81,6 +81,10 @@ constexpr uint32_t kFusedMinTiles = 16384;
 // The autotuner replaces the default plan only when a candidate is faster
 // by more than this fraction (timing noise must not flip the choice).
 constexpr float kTuneMargin = 0.03f;
+// Band plan: default band height, and sweeps per launch (the partials of a
+// launch are bands x sweeps pairs).
+constexpr uint32_t kBandDefaultRows = 16;
+constexpr uint32_t kBandChunk = 512;
 constexpr uint32_t kTuneRounds = 3;
 
 // Full-row fused shape: the widest chunk whose workgroup spans the row in at
@@ -147,6 +151,21 @@ static bool default_fused(uint32_t L, uint32_t* cw_out, uint32_t* rows_out) {
     return true;
 }
 
+// Band plan geometry: bands of a nominal `rows` rows, one wave per row up to
+// 16 waves a workgroup.
+uint32_t band_count(uint32_t L, uint32_t rows) { return (L + rows - 1u) / rows; }
+uint32_t band_threads(uint32_t L, uint32_t G) { return 64u * std::min<uint32_t>(16u, (L + G - 1u) / G); }
+uint32_t band_words(uint32_t L) { return (L / 8u + 7u) / 8u; }
+
+// Whether every band of the plan can be resident at once on the current
+// device (counted for the kernel variant with more registers).
+static bool bands_fit(uint32_t L, uint32_t rows) {
+    const uint32_t G = band_count(L, rows);
+    if (G < 2u || G > L) return false;
+    const uint32_t cap = bands_capacity(band_threads(L, G), band_lds_bytes(L, G, band_words(L)), true);
+    return cap >= G;
+}
+
 bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) {
     Plan pl{};
     const bool words = (L % 8u) == 0u;
@@ -186,6 +205,13 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
                 pl.rows = rows ? rows : (have ? dr : 8);
                 if (!fused_rows_supported(L, pl.cw, pl.rows)) return false;
             }
+            break;
+        case ISING_PLAN_BANDS:
+            if (!words || band_words(L) > kBandMaxWr) return false;
+            pl.kind = ISING_PLAN_BANDS;
+            pl.cw = 1;
+            pl.rows = rows ? rows : kBandDefaultRows;
+            if (!bands_fit(L, pl.rows)) return false;
             break;
         case ISING_PLAN_AUTO: {
             {
@@ -290,6 +316,37 @@ int ctx_prepare_plan(ising_ctx* ctx) {
         }
         ctx->owns_buf[1] = true;
     }
+    if (ctx->plan.kind == ISING_PLAN_BANDS) {
+        const uint32_t G = band_count(ctx->L, ctx->plan.rows);
+        if (G > ctx->band_cap) {
+            // earlier launches may still use the old slots and flags
+            if (ctx->band_cap) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->band_pub) (void)hipFree(ctx->band_pub);
+            if (ctx->band_part) (void)hipFree(ctx->band_part);
+            ctx->band_pub = nullptr;
+            ctx->band_part = nullptr;
+            ctx->band_cap = 0;
+            const size_t words = band_pub_words(G, band_words(ctx->L));
+            if (hipMalloc(&ctx->band_pub, words * sizeof(uint64_t)) != hipSuccess ||
+                hipMalloc(&ctx->band_part, (size_t)kBandChunk * G * 2 * sizeof(int64_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
+            }
+            // fresh slots carry tag 0, below every tag a launch waits for
+            HIP_TRY(ctx, hipMemsetAsync(ctx->band_pub, 0, words * sizeof(uint64_t), ctx->stream));
+            ctx->band_base = 0;
+            ctx->band_cap = G;
+        }
+        if (!ctx->band_err) {
+            if (hipMalloc(&ctx->band_err, sizeof(uint32_t)) != hipSuccess ||
+                hipHostMalloc(&ctx->band_err_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return ISING_ENOMEM;
+            }
+            *ctx->band_err_host = 0;
+            HIP_TRY(ctx, hipMemsetAsync(ctx->band_err, 0, sizeof(uint32_t), ctx->stream));
+        }
+    }
     uint32_t need = 0;
     const Planes pl = ctx_planes(ctx);
     if (ctx->plan.kind == ISING_PLAN_FUSED) need = fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
@@ -342,6 +399,44 @@ static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part0,
         ctx->cur ^= 1;
     }
     HIP_TRY(ctx, launch_reduce_partials(PartialReduce{part[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)}, ctx->stream));
+    return ISING_OK;
+}
+
+// n sweeps of the band plan: launches of up to `chunk` sweeps, each
+// followed by the sum of its bands' partials (at part) into ser.
+static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, uint32_t chunk) {
+    const uint32_t L = ctx->L, G = band_count(L, ctx->plan.rows);
+    const Planes pl = ctx_planes(ctx);
+    const uint32_t mode = bits_mode(ctx->table);
+    BandArgs a{};
+    a.p0 = reinterpret_cast<uint32_t*>(pl.p[0]);
+    a.p1 = reinterpret_cast<uint32_t*>(pl.p[1]);
+    a.L = L;
+    a.Hw = L / 8u;
+    a.Wr = band_words(L);
+    a.k0 = (uint32_t)ctx->p.seed;
+    a.k1 = (uint32_t)(ctx->p.seed >> 32);
+    a.pub = ctx->band_pub;
+    a.part = part;
+    a.err = ctx->band_err;
+    a.general = mode == 3u;
+    a.bl = bits_lattice(ctx->table, L, a.Hw, mode);
+    for (uint64_t done = 0; done < n;) {
+        const uint32_t m = (uint32_t)std::min<uint64_t>(n - done, chunk);
+        if ((uint64_t)ctx->band_base + 2ull * m >= 0xffffffffull) {
+            // the tags would wrap: clear every slot and count from 0 again
+            HIP_TRY(ctx, launch_bands_clear(ctx->band_pub, band_pub_words(ctx->band_cap, a.Wr), ctx->stream));
+            ctx->band_base = 0;
+        }
+        a.t0 = (uint32_t)(ctx->t + done);
+        a.n = m;
+        a.base = ctx->band_base;
+        HIP_TRY(ctx, launch_bands(a, G, band_threads(L, G), ctx->stream));
+        // every slot the launch used ends it tagged base + 2 m or base + 2 m - 1
+        ctx->band_base += 2u * m;
+        HIP_TRY(ctx, launch_bands_reduce(part, G, m, ser + 2 * done, ctx->stream));
+        done += m;
+    }
     return ISING_OK;
 }
 
@@ -604,6 +699,7 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
         case ISING_PLAN_FUSED_ROWS: rc = sweep_fused(ctx, n, ser, ctx->part[0], ctx->part[1]); break;
         case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser, ctx->part[0]); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, ser); break;
+        case ISING_PLAN_BANDS: rc = sweep_bands(ctx, n, ser, ctx->band_part, kBandChunk); break;
         default: return ISING_EUNSUPPORTED;
     }
     if (rc != ISING_OK) return rc;
@@ -646,6 +742,7 @@ int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
     if (ctx->plan.kind == ISING_PLAN_FUSED) pairs = 2 * fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
     if (ctx->plan.kind == ISING_PLAN_FUSED_ROWS) pairs = 2 * fused_rows_bands(ctx->L, ctx->plan.rows);
     if (ctx->plan.kind == ISING_PLAN_TWO_PASS) pairs = two_pass_blocks(ctx_planes(ctx), ctx->plan.cw);
+    if (ctx->plan.kind == ISING_PLAN_BANDS) pairs = band_count(ctx->L, ctx->plan.rows);  // per sweep
     if (pairs > ISING_STATIC_SCRATCH_PAIRS) return ISING_ERANGE;
     int64_t* sc = nullptr;
     if (pairs) {
@@ -662,6 +759,9 @@ int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
         }
         case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, series_dev, sc); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, series_dev); break;
+        case ISING_PLAN_BANDS:
+            rc = sweep_bands(ctx, n, series_dev, sc, std::min<uint32_t>(kBandChunk, ISING_STATIC_SCRATCH_PAIRS / pairs));
+            break;
         case ISING_PLAN_RESIDENT: {
             BatchItem it;
             fill_batch_item(ctx, n, false, it);
@@ -717,6 +817,22 @@ static int ensure_canonical(ising_ctx* ctx) {
     return ISING_OK;
 }
 
+// The band plan's edge waits give up only when a neighbouring band stopped
+// publishing (the bands were not all resident): the launch's results are
+// then not valid. Copy its mark back with a read-back, check it after.
+static int enqueue_band_check(ising_ctx* ctx) {
+    if (ctx->band_err)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->band_err_host, ctx->band_err, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+    return ISING_OK;
+}
+
+static int band_check(ising_ctx* ctx) {
+    if (ctx->band_err_host && *ctx->band_err_host)
+        return ctx_fail(ctx, hipErrorLaunchTimeOut, "band plan: a wait for a neighbouring band gave up");
+    return ISING_OK;
+}
+
 int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;
@@ -726,8 +842,10 @@ int ising_copy_spins(ising_ctx* ctx, int8_t* host, size_t n) {
     if (rc != ISING_OK) return rc;
     HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(host, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
+    rc = enqueue_band_check(ctx);
+    if (rc != ISING_OK) return rc;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    return ISING_OK;
+    return band_check(ctx);
 }
 
 int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t) {
@@ -798,7 +916,7 @@ static int enqueue_readback(ising_ctx* ctx, uint32_t want, bool full, int64_t* s
         HIP_TRY(ctx, launch_to_canonical(ctx_planes(ctx), ctx->canon, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(bytes, ctx->canon, N, hipMemcpyDeviceToHost, ctx->stream));
     }
-    return ISING_OK;
+    return enqueue_band_check(ctx);
 }
 
 int ising_prefetch_observables(ising_ctx* ctx, uint32_t want) {
@@ -879,6 +997,8 @@ int ising_observables(ising_ctx* ctx, ising_obs* out, int64_t* bond_series, int6
         if (rc != ISING_OK) return rc;
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     }
+    rc = band_check(ctx);
+    if (rc != ISING_OK) return rc;
     const uint64_t hsh = hash ? fnv1a64(bytes, N) : 0;
     const int64_t* last = full ? ser + 2 * (len - 1) : ser;
     const int64_t bm[2] = {last[0], last[1]};
@@ -941,7 +1061,7 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;
-    if (plan == ISING_PLAN_AUTO || plan > ISING_PLAN_FUSED_ROWS) return ISING_EINVAL;
+    if (plan == ISING_PLAN_AUTO || plan > ISING_PLAN_BANDS) return ISING_EINVAL;
     Plan pl;
     if (!plan_for(ctx->L, plan, cw, rows, &pl)) return ISING_EUNSUPPORTED;
     ctx_drop_graphs(ctx);
@@ -974,6 +1094,9 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
         for (uint32_t cw : cws)
             if (plan_for(L, ISING_PLAN_TWO_PASS, cw, 0, &pl)) cands.push_back(pl);
         if (L <= 1024 && plan_for(L, ISING_PLAN_RESIDENT, 0, 0, &pl)) cands.push_back(pl);
+        static const uint32_t brs[4] = {4, 8, 16, 32};
+        for (uint32_t r : brs)
+            if (plan_for(L, ISING_PLAN_BANDS, 0, r, &pl)) cands.push_back(pl);
     }
     // scratch context over a copy of the lattice, same table and seed
     ising_params p = ctx->p;
@@ -1233,6 +1356,10 @@ int ising_destroy(ising_ctx* ctx) {
     if (ctx->demon) (void)hipFree(ctx->demon);
     if (ctx->demon_alt) (void)hipFree(ctx->demon_alt);
     if (ctx->cpart) (void)hipFree(ctx->cpart);
+    if (ctx->band_pub) (void)hipFree(ctx->band_pub);
+    if (ctx->band_part) (void)hipFree(ctx->band_part);
+    if (ctx->band_err) (void)hipFree(ctx->band_err);
+    if (ctx->band_err_host) (void)hipHostFree(ctx->band_err_host);
     for (int k = 0; k < 2; ++k)
         if (ctx->cfpart[k]) (void)hipFree(ctx->cfpart[k]);
     if (ctx->scratch) (void)hipFree(ctx->scratch);

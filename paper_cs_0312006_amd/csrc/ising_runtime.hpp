@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "ising.h"
+#include "ising_bands.hpp"
 #include "ising_launch.hpp"
 
 namespace ising {
@@ -71,6 +72,17 @@ struct ising_ctx {
     ising::SweepHeader* ghdr = nullptr;
     int64_t* gpart = nullptr;
     size_t gpart_pairs = 0;
+    // Band-resident plan: tagged edge-row slots (2 x bands x 2 rows; the
+    // tag of the last half-sweep published is band_base, growing across
+    // launches), per-band partials of up to kBandChunk sweeps, the timeout
+    // mark of the edge waits and its pinned host copy; sized for band_cap
+    // bands.
+    uint64_t* band_pub = nullptr;
+    int64_t* band_part = nullptr;
+    uint32_t* band_err = nullptr;
+    uint32_t* band_err_host = nullptr;
+    uint32_t band_cap = 0;
+    uint32_t band_base = 0;
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;
     hipError_t last_hip = hipSuccess;

@@ -1,0 +1,135 @@
+"""GPU parity of the band-resident plan against the oracle: lattice sides
+with full and partial last bit words, band heights from one row (a wave
+that holds both edges of its band) to 32 rows and ragged bands (heights
+differing by one), h = 0 and h != 0, J < 0, zero thresholds, cold and
+hot starts, calls that cross the per-launch sweep limit, switches into
+and out of the plan (which reuse or regrow its edge slots and flags), and
+calls after a batched sweep moved the lattice."""
+import numpy as np
+import pytest
+
+from paper_cs_0312006_amd import workloads as W
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_cs_0312006_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def o():
+    from oracle import ref
+    orc = ref.Oracle()
+    orc.set_threads(G.host_threads())
+    return orc
+
+
+def _bands(b, run, rows, chunks):
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    try:
+        b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, rows)
+        assert b.ising_plan_info(ctx) == (b.ISING_PLAN_BANDS, 1, rows)
+        for k in chunks:
+            b.ising_sweep(ctx, k)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        spins = b.ising_copy_spins(ctx, run.L)
+    finally:
+        b.ising_destroy(ctx)
+    return {"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}
+
+
+CASES = [
+    # L, J, h, T, p_up, seed, band rows, calls
+    (16, 1.0, 0.0, 2.269185, 0.5, 3, 1, [4, 5]),       # 16 one-row bands
+    (16, 1.0, 0.1, 2.0, 0.5, 4, 8, [9]),               # two bands
+    (64, 1.0, 0.0, 2.269185, 0.5, 5, 3, [6, 1, 5]),    # 22 bands of 2 or 3 rows
+    (136, 1.0, 0.1, 1.8, 0.5, 7, 4, [7, 5]),           # 17 quads a row: 4 valid bits in the last word
+    (256, -1.0, 0.0, 2.0, 1.0, 9, 16, [12]),           # J < 0, cold start
+    (512, 0.5, -0.2, 2.5, 0.3, 11, 8, [5, 7]),
+    (1000, 1.0, 0.0, 2.269185, 0.5, 12, 5, [6, 6]),    # 125 quads a row: 20 valid bits in the last word
+    (1024, 1.0, 0.0, 0.2, 0.5, 13, 16, [10]),          # zero thresholds
+    (2048, 1.0, 0.05, 2.269185, 0.5, 15, 32, [4, 8]),
+    (4096, 1.0, 0.0, 2.269185, 0.5, 7, 16, [5, 7]),
+    (4096, 1.0, 0.1, 1.5, 0.5, 17, 8, [6, 6]),
+    (4096, 1.0, 0.0, 1e300, 0.5, 18, 4, [3]),          # every proposal accepted
+]
+
+
+@pytest.mark.parametrize("L,J,h,T,p_up,seed,rows,chunks", CASES)
+def test_bands_equal_oracle(b, o, L, J, h, T, p_up, seed, rows, chunks):
+    run = W.Run(L=L, J=J, h=h, T=T, seed=seed, p_up=p_up, sweeps=sum(chunks))
+    G.log(f"bands L={L} rows={rows} J={J} h={h} T={T} calls={chunks}")
+    G.assert_same(_bands(b, run, rows, chunks), G.oracle_run(o, run), f"bands L={L} rows={rows}")
+
+
+def test_bands_across_launch_limit(b, o):
+    """1100 sweeps in two calls: launches of at most 512 sweeps, each
+    resuming from the flags the previous one left."""
+    run = W.Run(L=64, h=0.05, T=2.4, seed=21, sweeps=1100)
+    G.log("bands L=64 1100 sweeps in calls of 600 and 500")
+    G.assert_same(_bands(b, run, 2, [600, 500]), G.oracle_run(o, run), "bands 1100 sweeps")
+
+
+def test_switches_into_and_out_of_bands(b, o):
+    run = W.Run(L=512, h=0.02, T=2.3, seed=23, sweeps=24)
+    ref = G.oracle_run(o, run)
+    ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
+    try:
+        steps = [(b.ISING_PLAN_FUSED_ROWS, 0, 0, 5), (b.ISING_PLAN_BANDS, 0, 16, 6), (b.ISING_PLAN_TWO_PASS, 0, 0, 4),
+                 (b.ISING_PLAN_BANDS, 0, 4, 3), (b.ISING_PLAN_BANDS, 0, 32, 2), (b.ISING_PLAN_FUSED, 0, 0, 4)]
+        for plan, cw, rows, n in steps:
+            G.log(f"switch to plan {plan} rows {rows} for {n} sweeps")
+            b.ising_plan_set(ctx, plan, cw, rows)
+            b.ising_sweep(ctx, n)
+        obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        got = {"spins": b.ising_copy_spins(ctx, run.L), "B": B, "M": M, "hash": obs.lattice_hash}
+    finally:
+        b.ising_destroy(ctx)
+    G.assert_same(got, ref, "plan switches through bands")
+
+
+def test_bands_after_batched_sweeps(b, o):
+    """A stepped batch leaves the lattice in the other buffer; the band plan
+    then continues from there."""
+    runs = [W.Run(L=1024, seed=31 + k, T=2.0 + 0.3 * k, sweeps=9) for k in range(3)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
+    try:
+        for c in ctxs:
+            b.ising_plan_set(c, b.ISING_PLAN_BANDS, 0, 16)
+            b.ising_sweep(c, 2)
+        G.log("bands then stepped batch then bands")
+        b.ising_sweep_batch_plan(ctxs, [4] * 3, plan=b.ISING_BATCH_STEPPED)
+        for c in ctxs:
+            b.ising_sweep(c, 3)
+        for r, c in zip(runs, ctxs):
+            obs, B, M = b.ising_observables(c, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            got = {"spins": b.ising_copy_spins(c, r.L), "B": B, "M": M, "hash": obs.lattice_hash}
+            G.assert_same(got, G.oracle_run(o, r), f"bands around a batch T={r.T}")
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
+
+
+def test_band_plan_limits(b):
+    """Sides whose rows do not fit one wave, or heights leaving fewer than
+    two bands, are refused; the context keeps its plan."""
+    ctx = b.ising_create(8192, 1.0, 0.0, 2.269185, 1, 0.5)
+    try:
+        before = b.ising_plan_info(ctx)
+        with pytest.raises(b.IsingError) as e:
+            b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, 16)
+        assert e.value.code == b.ISING_EUNSUPPORTED
+        assert b.ising_plan_info(ctx) == before
+    finally:
+        b.ising_destroy(ctx)
+    ctx = b.ising_create(64, 1.0, 0.0, 2.269185, 1, 0.5)
+    try:
+        with pytest.raises(b.IsingError):
+            b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, 64)
+    finally:
+        b.ising_destroy(ctx)

@@ -56,6 +56,9 @@ def test_static_sweeps_equal_ising_sweep(b):
         (1024, b.ISING_PLAN_FUSED, 1, 8, -1.0, 0.05, 3.0, 9, 7),
         (64, b.ISING_PLAN_RESIDENT, 0, 0, 1.0, 0.0, 2.269185, 10, 6),
         (34, b.ISING_PLAN_GENERIC, 0, 0, 1.0, 0.2, 1.5, 11, 5),
+        (4096, b.ISING_PLAN_BANDS, 0, 16, 1.0, 0.0, 2.269185, 12, 10),
+        # 256 one-row bands: 256 pairs a sweep, launches of 256 sweeps
+        (256, b.ISING_PLAN_BANDS, 0, 1, 1.0, 0.1, 2.0, 13, 600),
     ]
     for L, plan, cw, rows, J, h, T, seed, n in cases:
         G.log(f"static scratch L={L} plan={plan}")
