@@ -52,11 +52,11 @@ PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
 # plan runs (profiles/k_batch_bits_batched_1024.md, one dispatch of 2000
 # sweeps) and the stepped plan's fused walk (profiles/k_multi_fused_batched_1024.md,
 # mean of 160 dispatches, 16-row tiles)
-BATCH_FILES = ("ising_batch.hip", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_BATCH_SOURCES = "5437613bc3025381"
+BATCH_FILES = ("ising_batch.hip", "ising_bits.hpp", "ising_device.hpp", "ising_launch.hpp")
+PROFILED_BATCH_SOURCES = "e86f8f0d0ff597dc"
 PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
                   "valu_lane_ops_per_attempt": 192905902547.0 * 64 / (388630784 * 2000),
-                  "valu_busy_rocprof": 0.928}
+                  "valu_busy_rocprof": 0.932}
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
 PROFILED_MULTI_FUSED_SOURCES = "3e199830c7ada852"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
@@ -268,6 +268,16 @@ def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
     return res, hashes
 
 
+def warm_up(b, ctx, run):
+    """Series room for the timed calls, a few untimed sweeps (the context's
+    first-call allocations, clock ramp), then the context back at the run's
+    initial state, plan kept."""
+    b.ising_reserve(ctx, run.sweeps + 2000 + 20)
+    b.ising_sweep(ctx, 20)
+    b.ising_observables(ctx, 0)
+    b.ising_reset(ctx, run.L, run.J, run.h, run.T, run.seed, run.p_up)
+
+
 def run_small_configs(b, torch, stream):
     """The 64^2 config (1000 sweeps) and the three 4096^2 configs (2000
     sweeps each): throughput over the whole run with the autotuned plan, and
@@ -281,6 +291,7 @@ def run_small_configs(b, torch, stream):
         try:
             b.ising_tune(ctx, 50)
             plan = b.ising_plan_info(ctx)
+            warm_up(b, ctx, run)
             b.ising_observables(ctx, b.ISING_OBS_SERIES)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -301,6 +312,31 @@ def run_small_configs(b, torch, stream):
                     "value": run.attempts() / whole / 1e9, "unit": "attempts/ns (host clock, incl. series copy)",
                     "s": whole, "chunk10_p50_us": float(np.percentile(lat, 50) * 1e6),
                     "chunk10_p99_us": float(np.percentile(lat, 99) * 1e6)})
+    return out
+
+
+def run_c1(b, torch, stream):
+    """The three 4096^2 configs on the default plan (no tuning trials, no
+    latency calls): 2000 sweeps each, for profiling the sweep kernel alone."""
+    from paper_cs_0312006_amd import workloads as W
+    out = []
+    for run in W.C1:
+        ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up, stream=stream.cuda_stream)
+        try:
+            plan = b.ising_plan_info(ctx)
+            warm_up(b, ctx, run)
+            b.ising_observables(ctx, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.ising_sweep(ctx, run.sweeps)
+            b.ising_observables(ctx, b.ISING_OBS_SERIES)
+            whole = time.perf_counter() - t0
+        finally:
+            b.ising_destroy(ctx)
+        out.append({"workload": f"ising2d {run.L}x{run.L} T={run.T} seed {run.seed}, {run.sweeps} sweeps",
+                    "plan": {"kind": plan[0], "chunk_words": plan[1], "tile_rows": plan[2]},
+                    "value": run.attempts() / whole / 1e9, "unit": "attempts/ns (host clock, incl. series copy)",
+                    "s": whole})
     return out
 
 
@@ -606,7 +642,7 @@ def main():
     ap.add_argument("--creutz-sweeps", type=int, default=100)
     ap.add_argument("--only", default=None,
                     choices=["creutz", "percolation", "percolation-media", "micro", "batched", "batched-stepped",
-                             "batched-resident", "served", "fifo", "small-configs"],
+                             "batched-resident", "served", "fifo", "small-configs", "c1"],
                     help="run one extra leg alone (for profiling it); prints that leg's JSON only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB copy (for scaling rocprofv3 byte counters)")
@@ -636,6 +672,8 @@ def main():
             leg = run_fifo(b, float(args.served_rates.split(",")[0]), args.served_requests)
         elif args.only == "small-configs":
             leg = run_small_configs(b, torch, stream)
+        elif args.only == "c1":
+            leg = run_c1(b, torch, stream)
         elif args.only.startswith("batched"):
             leg, _ = run_batched(b, torch, stream, 1024, args.batched_sweeps, 0,
                                  plan={"batched": 0, "batched-resident": 1, "batched-stepped": 2}[args.only])
@@ -653,7 +691,7 @@ def main():
     attempts = run.L * run.L * steps
     value = attempts / ms / 1e6  # attempts per ns
     launch_ms = ms / steps      # one fused launch per sweep (plus one tiny reduce per call)
-    plan_names = {1: "two-pass", 2: "fused", 3: "resident", 4: "generic", 5: "fused-rows"}
+    plan_names = {1: "two-pass", 2: "fused", 3: "resident", 4: "generic", 5: "fused-rows", 6: "bands"}
     plan = head["plan"]
     alg_bytes = 2.0 * run.L * run.L if plan[0] in (2, 5) else 3.0 * run.L * run.L
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9

@@ -63,10 +63,12 @@ extern "C" {
 #define ISING_MAX_L 65536u     /* counter word 0 holds site/8: L*L/8 must fit 32 bits */
 
 /* Plan selection (ising_params.flags, low byte). AUTO picks per lattice side:
- * the workgroup-resident kernel for small sides, the fused one-pass sweep by
- * full-row workgroups where a row fits one workgroup, the fused sweep by
- * wave tiles for larger sides, the two-pass in-place sweep otherwise. The
- * others force a path (ISING_EUNSUPPORTED if the side does not fit it). */
+ * the workgroup-resident kernel for small sides, the band-resident plan for
+ * sides 512 to 4096 (about one band of rows per compute unit), the fused
+ * one-pass sweep by full-row workgroups where a row fits one workgroup, the
+ * fused sweep by wave tiles for larger sides, the two-pass in-place sweep
+ * otherwise. The others force a path (ISING_EUNSUPPORTED if the side does
+ * not fit it). */
 #define ISING_PLAN_AUTO 0u
 #define ISING_PLAN_TWO_PASS 1u  /* one launch per colour, in place */
 #define ISING_PLAN_FUSED 2u     /* one launch per sweep, ping-pong buffers; a wave per tile */

@@ -48,8 +48,8 @@ namespace ising {
 namespace {
 
 constexpr uint32_t kBandMaxWaves = 16;
-// Polls of an edge word (each followed by a short sleep) before a wait gives up:
-// about a second.
+// Polls of an edge word (each a read of its coherent copy and a short sleep)
+// before a wait gives up: several seconds.
 constexpr uint32_t kBandMaxPolls = 1u << 24;
 
 __device__ __forceinline__ void put_word(uint64_t* p, uint32_t tag, uint32_t w) {

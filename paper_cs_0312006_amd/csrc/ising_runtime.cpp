@@ -81,9 +81,13 @@ constexpr uint32_t kFusedMinTiles = 16384;
 // The autotuner replaces the default plan only when a candidate is faster
 // by more than this fraction (timing noise must not flip the choice).
 constexpr float kTuneMargin = 0.03f;
-// Band plan: default band height, and sweeps per launch (the partials of a
-// launch are bands x sweeps pairs).
-constexpr uint32_t kBandDefaultRows = 16;
+// Band plan: sides it serves by default, and sweeps per launch (the
+// partials of a launch are bands x sweeps pairs). Its default band height
+// gives about one band per compute unit: one band a CU measured fastest
+// from 512 to 4096 (fewer bands leave CUs idle, more put unequal numbers of
+// bands on CUs, and each band's half-sweep is bound by the latency of its
+// own rows and of the edge exchange, not by the chip's throughput).
+constexpr uint32_t kBandMinDefaultL = 512;
 constexpr uint32_t kBandChunk = 512;
 constexpr uint32_t kTuneRounds = 3;
 
@@ -166,6 +170,16 @@ static bool bands_fit(uint32_t L, uint32_t rows) {
     return cap >= G;
 }
 
+static uint32_t band_default_rows(uint32_t L) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    return std::max<uint32_t>(1u, (L + (uint32_t)cus - 1u) / (uint32_t)cus);
+}
+
 bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) {
     Plan pl{};
     const bool words = (L % 8u) == 0u;
@@ -210,7 +224,7 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
             if (!words || band_words(L) > kBandMaxWr) return false;
             pl.kind = ISING_PLAN_BANDS;
             pl.cw = 1;
-            pl.rows = rows ? rows : kBandDefaultRows;
+            pl.rows = rows ? rows : band_default_rows(L);
             if (!bands_fit(L, pl.rows)) return false;
             break;
         case ISING_PLAN_AUTO: {
@@ -224,6 +238,7 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
             }
             if (!words) return plan_for(L, ISING_PLAN_GENERIC, 0, 0, out);
             if (L <= kResidentMaxL) return plan_for(L, ISING_PLAN_RESIDENT, 0, 0, out);
+            if (L >= kBandMinDefaultL && plan_for(L, ISING_PLAN_BANDS, 0, 0, out)) return true;
             if (plan_for(L, ISING_PLAN_FUSED_ROWS, 0, 0, out)) return true;
             if (plan_for(L, ISING_PLAN_FUSED, 0, 0, out)) return true;
             return plan_for(L, ISING_PLAN_TWO_PASS, 0, 0, out);
@@ -322,13 +337,10 @@ int ctx_prepare_plan(ising_ctx* ctx) {
             // earlier launches may still use the old slots and flags
             if (ctx->band_cap) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
             if (ctx->band_pub) (void)hipFree(ctx->band_pub);
-            if (ctx->band_part) (void)hipFree(ctx->band_part);
             ctx->band_pub = nullptr;
-            ctx->band_part = nullptr;
             ctx->band_cap = 0;
             const size_t words = band_pub_words(G, band_words(ctx->L));
-            if (hipMalloc(&ctx->band_pub, words * sizeof(uint64_t)) != hipSuccess ||
-                hipMalloc(&ctx->band_part, (size_t)kBandChunk * G * 2 * sizeof(int64_t)) != hipSuccess) {
+            if (hipMalloc(&ctx->band_pub, words * sizeof(uint64_t)) != hipSuccess) {
                 (void)hipGetLastError();
                 return ISING_ENOMEM;
             }
@@ -399,6 +411,27 @@ static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part0,
         ctx->cur ^= 1;
     }
     HIP_TRY(ctx, launch_reduce_partials(PartialReduce{part[(n - 1) & 1], n_tiles, ser + 2 * (n - 1)}, ctx->stream));
+    return ISING_OK;
+}
+
+// The band plan's partials for launches of kBandChunk sweeps, allocated on
+// the first ising_sweep (a context that only runs in batches never needs
+// them, and ising_sweep_static uses the library's array instead).
+static int ctx_band_part(ising_ctx* ctx) {
+    const uint32_t G = band_count(ctx->L, ctx->plan.rows);
+    if (ctx->band_part && ctx->band_part_cap >= G) return ISING_OK;
+    if (ctx->band_part) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->band_part);
+        ctx->band_part = nullptr;
+        ctx->band_part_cap = 0;
+    }
+    if (hipMalloc(&ctx->band_part, (size_t)kBandChunk * G * 2 * sizeof(int64_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->band_part = nullptr;
+        return ISING_ENOMEM;
+    }
+    ctx->band_part_cap = G;
     return ISING_OK;
 }
 
@@ -699,7 +732,10 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
         case ISING_PLAN_FUSED_ROWS: rc = sweep_fused(ctx, n, ser, ctx->part[0], ctx->part[1]); break;
         case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser, ctx->part[0]); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, ser); break;
-        case ISING_PLAN_BANDS: rc = sweep_bands(ctx, n, ser, ctx->band_part, kBandChunk); break;
+        case ISING_PLAN_BANDS:
+            rc = ctx_band_part(ctx);
+            if (rc == ISING_OK) rc = sweep_bands(ctx, n, ser, ctx->band_part, kBandChunk);
+            break;
         default: return ISING_EUNSUPPORTED;
     }
     if (rc != ISING_OK) return rc;
@@ -1094,9 +1130,11 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
         for (uint32_t cw : cws)
             if (plan_for(L, ISING_PLAN_TWO_PASS, cw, 0, &pl)) cands.push_back(pl);
         if (L <= 1024 && plan_for(L, ISING_PLAN_RESIDENT, 0, 0, &pl)) cands.push_back(pl);
-        static const uint32_t brs[4] = {4, 8, 16, 32};
-        for (uint32_t r : brs)
-            if (plan_for(L, ISING_PLAN_BANDS, 0, r, &pl)) cands.push_back(pl);
+        const uint32_t brs[6] = {band_default_rows(L), 2, 4, 8, 16, 32};
+        for (uint32_t k = 0; k < 6; ++k) {
+            if (k > 0 && brs[k] == brs[0]) continue;
+            if (plan_for(L, ISING_PLAN_BANDS, 0, brs[k], &pl)) cands.push_back(pl);
+        }
     }
     // scratch context over a copy of the lattice, same table and seed
     ising_params p = ctx->p;

@@ -72,16 +72,18 @@ struct ising_ctx {
     ising::SweepHeader* ghdr = nullptr;
     int64_t* gpart = nullptr;
     size_t gpart_pairs = 0;
-    // Band-resident plan: tagged edge-row slots (2 x bands x 2 rows; the
-    // tag of the last half-sweep published is band_base, growing across
-    // launches), per-band partials of up to kBandChunk sweeps, the timeout
-    // mark of the edge waits and its pinned host copy; sized for band_cap
-    // bands.
+    // Band-resident plan: tagged edge-row slots for band_cap bands (2 x
+    // bands x 2 rows; the tag of the last half-sweep published is
+    // band_base, growing across launches), per-band partials of up to
+    // kBandChunk sweeps for band_part_cap bands (allocated by the first
+    // ising_sweep), the timeout mark of the edge waits and its pinned host
+    // copy.
     uint64_t* band_pub = nullptr;
     int64_t* band_part = nullptr;
     uint32_t* band_err = nullptr;
     uint32_t* band_err_host = nullptr;
     uint32_t band_cap = 0;
+    uint32_t band_part_cap = 0;
     uint32_t band_base = 0;
     uint64_t t = 0;              // next sweep index
     bool poisoned = false;

@@ -38,5 +38,6 @@ def test_headline_profile_only_for_profiled_sources(monkeypatch):
 def test_profile_summaries_exist():
     for name in ("k_fused_rows_ising2d_32768.md", "k_fused_ising2d_32768.md", "k_fused_ising2d_4096.md",
                  "k_creutz_fused_creutz_32768.md", "k_batch_bits_batched_1024.md", "k_multi_fused_batched_1024.md",
-                 "k_multi_fused_served_stream.md", "k_vec_micro.md", "k_perc_relax_percolation_32768.md"):
+                 "k_multi_fused_served_stream.md", "k_vec_micro.md", "k_perc_relax_percolation_32768.md",
+                 "k_bands_ising2d_4096.md"):
         assert os.path.isfile(os.path.join(ROOT, "profiles", name)), name

@@ -45,17 +45,20 @@ def _ctx_result(b, ctx, L):
 def test_c1_4096_all_2000_sweeps(b, o, k):
     """4096 x 4096 at T in {1.5, 2.269185, 3.5}, seed 7, 2000 sweeps: the
     final lattice, its hash and all 2000 (B_t, M_t) equal a full oracle run,
-    in the default plan and in the plan the autotuner picks (50-sweep
-    trials, as the benchmark does)."""
+    in the default plan (band-resident), in the plan the autotuner picks
+    (50-sweep trials, as the benchmark does) and in the fused wave-tile
+    plan."""
     run = W.C1[k]
     G.log(f"C1 4096 T={run.T} 2000 sweeps: oracle")
     ref = G.oracle_run(o, run)
-    for tuned in (False, True):
-        G.log(f"C1 4096 T={run.T} 2000 sweeps: GPU ({'tuned' if tuned else 'default'} plan)")
+    for how in ("default", "tuned", "fused"):
+        G.log(f"C1 4096 T={run.T} 2000 sweeps: GPU ({how} plan)")
         ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
         try:
-            if tuned:
+            if how == "tuned":
                 b.ising_tune(ctx, 50)
+            elif how == "fused":
+                b.ising_plan_set(ctx, b.ISING_PLAN_FUSED, 1, 8)
             b.ising_sweep(ctx, run.sweeps)
             g = _ctx_result(b, ctx, run.L)
             plan = tuple(b.ising_plan_info(ctx))

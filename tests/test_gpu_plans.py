@@ -401,7 +401,8 @@ def test_autotune_keeps_lattice_and_picks_a_plan(b, o):
     after = b.ising_copy_spins(ctx, run.L)
     assert np.array_equal(before, after)
     plan = b.ising_plan_info(ctx)
-    assert plan[0] in (b.ISING_PLAN_FUSED, b.ISING_PLAN_FUSED_ROWS, b.ISING_PLAN_TWO_PASS, b.ISING_PLAN_RESIDENT)
+    assert plan[0] in (b.ISING_PLAN_FUSED, b.ISING_PLAN_FUSED_ROWS, b.ISING_PLAN_TWO_PASS, b.ISING_PLAN_RESIDENT,
+                       b.ISING_PLAN_BANDS)
     b.ising_sweep(ctx, 4)
     obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
     spins = b.ising_copy_spins(ctx, run.L)
