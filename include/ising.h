@@ -77,8 +77,11 @@ extern "C" {
 #define ISING_PLAN_FUSED_ROWS 5u /* as FUSED, a workgroup per band of whole rows (L/8 <= 16 * 64 * cw) */
 #define ISING_PLAN_BANDS 6u      /* the lattice split into bands of whole rows, one workgroup each, all
                                    * resident at once; each band stays in LDS at one bit per site for
-                                   * every sweep of a call, bands trade edge rows after each half-sweep
+                                   * every sweep of a launch, bands trade edge rows after each half-sweep
                                    * (L % 8 == 0, L <= 4096) */
+/* Sweeps of one band-plan launch (the lattice crosses HBM once per launch);
+ * longer calls are split into launches of this many sweeps. */
+#define ISING_BAND_SWEEPS_PER_LAUNCH 512u
 
 /* Model and run parameters (Section 2.2: L x L lattice, coupling J, field h,
  * temperature T, spin-up probability p_up of the initial state). */
@@ -303,7 +306,8 @@ int ising_series_averages(const int64_t* bond_series, const int64_t* mag_series,
                           uint32_t L, double J, double h, ising_averages* out);
 
 /* Plan the context runs with: ISING_PLAN_* and, for tunable plans, the
- * chunk width in 32-bit words and the rows per thread. */
+ * chunk width in 32-bit words (for the band plan: rows per wave) and the
+ * tile or band height in rows. */
 int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
                     uint32_t* rows_per_thread);
 
@@ -312,8 +316,8 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
  * {4, 8, 16, 32, 64, 128}; for ISING_PLAN_FUSED_ROWS cw and the band height
  * rows in {8, 16, 32, 64, 128}, with L/8 / (64 cw) <= 16; for
  * ISING_PLAN_BANDS the band height rows >= 1, giving ceil(L / rows) >= 2
- * bands that must all fit the device at once, cw ignored; 0 picks a
- * default). Switching to the fused plan may allocate a second lattice
+ * bands that must all fit the device at once, and cw in {1, 2, 4} rows per
+ * wave; 0 picks a default). Switching to the fused plan may allocate a second lattice
  * buffer, to the band plan its edge-row slots and flags. Results do not
  * depend on the plan.
  * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */

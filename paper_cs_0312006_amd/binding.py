@@ -32,6 +32,7 @@ ISING_PLAN_RESIDENT = 3
 ISING_PLAN_GENERIC = 4
 ISING_PLAN_FUSED_ROWS = 5
 ISING_PLAN_BANDS = 6
+ISING_BAND_SWEEPS_PER_LAUNCH = 512
 
 ISING_BATCH_AUTO = 0
 ISING_BATCH_RESIDENT = 1

@@ -88,7 +88,7 @@ constexpr float kTuneMargin = 0.03f;
 // bands on CUs, and each band's half-sweep is bound by the latency of its
 // own rows and of the edge exchange, not by the chip's throughput).
 constexpr uint32_t kBandMinDefaultL = 512;
-constexpr uint32_t kBandChunk = 512;
+constexpr uint32_t kBandChunk = ISING_BAND_SWEEPS_PER_LAUNCH;
 constexpr uint32_t kTuneRounds = 3;
 
 // Full-row fused shape: the widest chunk whose workgroup spans the row in at
@@ -155,18 +155,21 @@ static bool default_fused(uint32_t L, uint32_t* cw_out, uint32_t* rows_out) {
     return true;
 }
 
-// Band plan geometry: bands of a nominal `rows` rows, one wave per row up to
-// 16 waves a workgroup.
+// Band plan geometry: bands of a nominal `rows` rows, `per_wave` rows a wave
+// (at most 16 waves a workgroup; a wave runs its rows one after another).
 uint32_t band_count(uint32_t L, uint32_t rows) { return (L + rows - 1u) / rows; }
-uint32_t band_threads(uint32_t L, uint32_t G) { return 64u * std::min<uint32_t>(16u, (L + G - 1u) / G); }
+uint32_t band_threads(uint32_t L, uint32_t G, uint32_t per_wave) {
+    const uint32_t rows = (L + G - 1u) / G;
+    return 64u * std::min<uint32_t>(16u, (rows + per_wave - 1u) / per_wave);
+}
 uint32_t band_words(uint32_t L) { return (L / 8u + 7u) / 8u; }
 
 // Whether every band of the plan can be resident at once on the current
 // device (counted for the kernel variant with more registers).
-static bool bands_fit(uint32_t L, uint32_t rows) {
+static bool bands_fit(uint32_t L, uint32_t rows, uint32_t per_wave) {
     const uint32_t G = band_count(L, rows);
     if (G < 2u || G > L) return false;
-    const uint32_t cap = bands_capacity(band_threads(L, G), band_lds_bytes(L, G, band_words(L)), true);
+    const uint32_t cap = bands_capacity(band_threads(L, G, per_wave), band_lds_bytes(L, G, band_words(L)), true);
     return cap >= G;
 }
 
@@ -223,9 +226,10 @@ bool plan_for(uint32_t L, uint32_t kind, uint32_t cw, uint32_t rows, Plan* out) 
         case ISING_PLAN_BANDS:
             if (!words || band_words(L) > kBandMaxWr) return false;
             pl.kind = ISING_PLAN_BANDS;
-            pl.cw = 1;
+            pl.cw = cw ? cw : 1;  // rows a wave
+            if (pl.cw != 1 && pl.cw != 2 && pl.cw != 4) return false;
             pl.rows = rows ? rows : band_default_rows(L);
-            if (!bands_fit(L, pl.rows)) return false;
+            if (!bands_fit(L, pl.rows, pl.cw)) return false;
             break;
         case ISING_PLAN_AUTO: {
             {
@@ -464,7 +468,7 @@ static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, 
         a.t0 = (uint32_t)(ctx->t + done);
         a.n = m;
         a.base = ctx->band_base;
-        HIP_TRY(ctx, launch_bands(a, G, band_threads(L, G), ctx->stream));
+        HIP_TRY(ctx, launch_bands(a, G, band_threads(L, G, ctx->plan.cw), ctx->stream));
         // every slot the launch used ends it tagged base + 2 m or base + 2 m - 1
         ctx->band_base += 2u * m;
         HIP_TRY(ctx, launch_bands_reduce(part, G, m, ser + 2 * done, ctx->stream));
@@ -1131,9 +1135,10 @@ int ising_tune(ising_ctx* ctx, uint32_t trial_sweeps) {
             if (plan_for(L, ISING_PLAN_TWO_PASS, cw, 0, &pl)) cands.push_back(pl);
         if (L <= 1024 && plan_for(L, ISING_PLAN_RESIDENT, 0, 0, &pl)) cands.push_back(pl);
         const uint32_t brs[6] = {band_default_rows(L), 2, 4, 8, 16, 32};
+        // one row a wave: two or four (fewer waves a SIMD) measured 12-80% slower
         for (uint32_t k = 0; k < 6; ++k) {
             if (k > 0 && brs[k] == brs[0]) continue;
-            if (plan_for(L, ISING_PLAN_BANDS, 0, brs[k], &pl)) cands.push_back(pl);
+            if (plan_for(L, ISING_PLAN_BANDS, 1, brs[k], &pl)) cands.push_back(pl);
         }
     }
     // scratch context over a copy of the lattice, same table and seed

@@ -37,6 +37,21 @@ def test_header_declares_the_four_core_calls():
         assert core in names
 
 
+def test_binding_constants_equal_the_headers(b):
+    """Every integer #define of include/*.h that the binding mirrors under
+    the same name has the same value there."""
+    checked = 0
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        for name, val in re.findall(r"^#define\s+(\w+)\s+\(?(-?(?:0x[0-9a-fA-F]+|\d+))u?\)?",
+                                    open(os.path.join(INCLUDE, h)).read(), re.M):
+            if hasattr(b, name):
+                assert getattr(b, name) == int(val, 0), name
+                checked += 1
+    assert checked >= 20
+
+
 def test_library_exports_every_declared_symbol(b):
     names = declared_functions()
     assert len(names) >= 10

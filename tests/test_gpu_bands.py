@@ -29,11 +29,11 @@ def o():
     return orc
 
 
-def _bands(b, run, rows, chunks):
+def _bands(b, run, rows, chunks, per_wave=1):
     ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
     try:
-        b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, rows)
-        assert b.ising_plan_info(ctx) == (b.ISING_PLAN_BANDS, 1, rows)
+        b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, per_wave, rows)
+        assert b.ising_plan_info(ctx) == (b.ISING_PLAN_BANDS, per_wave, rows)
         for k in chunks:
             b.ising_sweep(ctx, k)
         obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
@@ -44,27 +44,32 @@ def _bands(b, run, rows, chunks):
 
 
 CASES = [
-    # L, J, h, T, p_up, seed, band rows, calls
-    (16, 1.0, 0.0, 2.269185, 0.5, 3, 1, [4, 5]),       # 16 one-row bands
-    (16, 1.0, 0.1, 2.0, 0.5, 4, 8, [9]),               # two bands
-    (64, 1.0, 0.0, 2.269185, 0.5, 5, 3, [6, 1, 5]),    # 22 bands of 2 or 3 rows
-    (136, 1.0, 0.1, 1.8, 0.5, 7, 4, [7, 5]),           # 17 quads a row: 4 valid bits in the last word
-    (256, -1.0, 0.0, 2.0, 1.0, 9, 16, [12]),           # J < 0, cold start
-    (512, 0.5, -0.2, 2.5, 0.3, 11, 8, [5, 7]),
-    (1000, 1.0, 0.0, 2.269185, 0.5, 12, 5, [6, 6]),    # 125 quads a row: 20 valid bits in the last word
-    (1024, 1.0, 0.0, 0.2, 0.5, 13, 16, [10]),          # zero thresholds
-    (2048, 1.0, 0.05, 2.269185, 0.5, 15, 32, [4, 8]),
-    (4096, 1.0, 0.0, 2.269185, 0.5, 7, 16, [5, 7]),
-    (4096, 1.0, 0.1, 1.5, 0.5, 17, 8, [6, 6]),
-    (4096, 1.0, 0.0, 1e300, 0.5, 18, 4, [3]),          # every proposal accepted
+    # L, J, h, T, p_up, seed, band rows, rows a wave, calls
+    (16, 1.0, 0.0, 2.269185, 0.5, 3, 1, 1, [4, 5]),       # 16 one-row bands
+    (16, 1.0, 0.1, 2.0, 0.5, 4, 8, 1, [9]),               # two bands
+    (16, 1.0, 0.1, 2.0, 0.5, 4, 8, 4, [9]),               # two bands of two waves
+    (64, 1.0, 0.0, 2.269185, 0.5, 5, 3, 1, [6, 1, 5]),    # 22 bands of 2 or 3 rows
+    (64, 1.0, 0.0, 2.269185, 0.5, 5, 3, 2, [6, 1, 5]),    # one wave holding both edges of a 2-row band
+    (136, 1.0, 0.1, 1.8, 0.5, 7, 4, 1, [7, 5]),           # 17 quads a row: 4 valid bits in the last word
+    (256, -1.0, 0.0, 2.0, 1.0, 9, 16, 1, [12]),           # J < 0, cold start
+    (512, 0.5, -0.2, 2.5, 0.3, 11, 8, 1, [5, 7]),
+    (520, 1.0, 0.0, 2.269185, 0.5, 19, 7, 2, [4, 4]),     # 75 bands of 6 or 7 rows, waves of 2 rows
+    (1000, 1.0, 0.0, 2.269185, 0.5, 12, 5, 1, [6, 6]),    # 125 quads a row: 20 valid bits in the last word
+    (1024, 1.0, 0.0, 0.2, 0.5, 13, 16, 1, [10]),          # zero thresholds
+    (2048, 1.0, 0.05, 2.269185, 0.5, 15, 32, 1, [4, 8]),  # 16 waves of 2 rows
+    (2048, 1.0, 0.05, 2.269185, 0.5, 15, 32, 4, [4, 8]),
+    (4096, 1.0, 0.0, 2.269185, 0.5, 7, 16, 1, [5, 7]),
+    (4096, 1.0, 0.0, 2.269185, 0.5, 7, 16, 2, [5, 7]),
+    (4096, 1.0, 0.1, 1.5, 0.5, 17, 8, 1, [6, 6]),
+    (4096, 1.0, 0.0, 1e300, 0.5, 18, 4, 1, [3]),          # every proposal accepted
 ]
 
 
-@pytest.mark.parametrize("L,J,h,T,p_up,seed,rows,chunks", CASES)
-def test_bands_equal_oracle(b, o, L, J, h, T, p_up, seed, rows, chunks):
+@pytest.mark.parametrize("L,J,h,T,p_up,seed,rows,per_wave,chunks", CASES)
+def test_bands_equal_oracle(b, o, L, J, h, T, p_up, seed, rows, per_wave, chunks):
     run = W.Run(L=L, J=J, h=h, T=T, seed=seed, p_up=p_up, sweeps=sum(chunks))
-    G.log(f"bands L={L} rows={rows} J={J} h={h} T={T} calls={chunks}")
-    G.assert_same(_bands(b, run, rows, chunks), G.oracle_run(o, run), f"bands L={L} rows={rows}")
+    G.log(f"bands L={L} rows={rows} per_wave={per_wave} J={J} h={h} T={T} calls={chunks}")
+    G.assert_same(_bands(b, run, rows, chunks, per_wave), G.oracle_run(o, run), f"bands L={L} rows={rows}")
 
 
 def test_bands_across_launch_limit(b, o):
@@ -80,7 +85,7 @@ def test_switches_into_and_out_of_bands(b, o):
     ref = G.oracle_run(o, run)
     ctx = b.ising_create(run.L, run.J, run.h, run.T, run.seed, run.p_up)
     try:
-        steps = [(b.ISING_PLAN_FUSED_ROWS, 0, 0, 5), (b.ISING_PLAN_BANDS, 0, 16, 6), (b.ISING_PLAN_TWO_PASS, 0, 0, 4),
+        steps = [(b.ISING_PLAN_FUSED_ROWS, 0, 0, 5), (b.ISING_PLAN_BANDS, 2, 16, 6), (b.ISING_PLAN_TWO_PASS, 0, 0, 4),
                  (b.ISING_PLAN_BANDS, 0, 4, 3), (b.ISING_PLAN_BANDS, 0, 32, 2), (b.ISING_PLAN_FUSED, 0, 0, 4)]
         for plan, cw, rows, n in steps:
             G.log(f"switch to plan {plan} rows {rows} for {n} sweeps")
