@@ -147,7 +147,9 @@ int ising_create_in(const ising_params* params, void* dev_buf, size_t bytes, voi
 /* Enqueue n full sweeps (colour 0 then colour 1, Section 2.2) on the
  * context's stream, for sweep indices t .. t+n-1, and record (B_t, M_t)
  * after each. Asynchronous. n = 0 is a no-op. Errors: EINVAL (NULL ctx),
- * ERANGE (t + n > 2^32), ESTATE, ENOMEM (series buffer growth), EDEVICE. */
+ * ERANGE (t + n > 2^32), ESTATE, ENOMEM (series buffer growth), EDEVICE,
+ * EUNSUPPORTED (a band-plan context whose stream is being captured into a
+ * graph: capture ising_sweep_static instead). */
 int ising_sweep(ising_ctx* ctx, uint64_t n);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -167,8 +169,12 @@ int ising_sweep(ising_ctx* ctx, uint64_t n);
  * ordered by the caller. The fused plan needs 2 x its tiles pairs (32768^2
  * with 32-row tiles: 32768), the two-pass plan one per block, the band
  * plan one per band and sweep (its launches are split so that they fit; its
- * edge-row slots and flags were allocated when the plan was set); the
- * resident and per-site plans need none. Errors: EINVAL (NULL ctx or series_dev),
+ * edge-row slots were allocated when the plan was set); the resident and
+ * per-site plans need none. While the context's stream is being captured
+ * into a graph, a band-plan context's sweeps are enqueued as two-pass
+ * launches with one word per thread (the same results): a band launch's
+ * edge-row tags advance on the host with every launch, which a replayed
+ * graph would not do. Errors: EINVAL (NULL ctx or series_dev),
  * ERANGE (t + n > 2^32, or the plan needs more pairs than the array holds:
  * pick taller tiles with ising_plan_set), ESTATE, EDEVICE. */
 #define ISING_STATIC_SCRATCH_PAIRS 65536u

@@ -478,15 +478,17 @@ static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, 
 }
 
 // n sweeps of the two-pass plan; per-block partials in part (nb pairs).
-static int sweep_two_pass(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part) {
+// (cw: words per thread, 0 for the context's plan's.)
+static int sweep_two_pass(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, uint32_t cw = 0) {
     const uint32_t k0 = (uint32_t)ctx->p.seed, k1 = (uint32_t)(ctx->p.seed >> 32);
     const Planes pl = ctx_planes(ctx);
-    const uint32_t nb = two_pass_blocks(pl, ctx->plan.cw);
+    if (!cw) cw = ctx->plan.cw;
+    const uint32_t nb = two_pass_blocks(pl, cw);
     for (uint64_t k = 0; k < n; ++k) {
         const uint32_t t = (uint32_t)(ctx->t + k);
         PartialReduce red{nullptr, 0, nullptr};
         if (k > 0) red = PartialReduce{part, nb, ser + 2 * (k - 1)};
-        HIP_TRY(ctx, launch_two_pass(pl, ctx->table, ctx->exact, ctx->plan.cw, t, k0, k1, part, red, ctx->stream));
+        HIP_TRY(ctx, launch_two_pass(pl, ctx->table, ctx->exact, cw, t, k0, k1, part, red, ctx->stream));
     }
     HIP_TRY(ctx, launch_reduce_partials(PartialReduce{part, nb, ser + 2 * (n - 1)}, ctx->stream));
     return ISING_OK;
@@ -709,10 +711,24 @@ int ising_reserve(ising_ctx* ctx, uint64_t sweeps) {
     return ctx_reserve_series(ctx, sweeps);
 }
 
+// Whether work enqueued on s is being captured into a graph. The band plan
+// must not be captured: each launch's edge-row tags start from a base the
+// host advances per launch, so a replayed launch would find the slots
+// still holding the previous replay's words under the tags it waits for.
+static bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return st != hipStreamCaptureStatusNone;
+}
+
 int ising_sweep(ising_ctx* ctx, uint64_t n) {
     int rc = ctx_enter(ctx);
     if (rc != ISING_OK) return rc;
     if (n == 0) return ISING_OK;
+    if (ctx->plan.kind == ISING_PLAN_BANDS && stream_capturing(ctx->stream)) return ISING_EUNSUPPORTED;
     if (ctx->t + n > ((uint64_t)1 << 32)) return ISING_ERANGE;
     rc = ctx_reserve_series(ctx, n);
     if (rc != ISING_OK) return rc;
@@ -782,7 +798,10 @@ int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
     if (ctx->plan.kind == ISING_PLAN_FUSED) pairs = 2 * fused_tiles(ctx->L, ctx->plan.cw, ctx->plan.rows);
     if (ctx->plan.kind == ISING_PLAN_FUSED_ROWS) pairs = 2 * fused_rows_bands(ctx->L, ctx->plan.rows);
     if (ctx->plan.kind == ISING_PLAN_TWO_PASS) pairs = two_pass_blocks(ctx_planes(ctx), ctx->plan.cw);
-    if (ctx->plan.kind == ISING_PLAN_BANDS) pairs = band_count(ctx->L, ctx->plan.rows);  // per sweep
+    // under capture the band plan's sweeps run as two-pass launches
+    const bool bands_as_two_pass = ctx->plan.kind == ISING_PLAN_BANDS && stream_capturing(ctx->stream);
+    if (ctx->plan.kind == ISING_PLAN_BANDS)
+        pairs = bands_as_two_pass ? two_pass_blocks(ctx_planes(ctx), 1) : band_count(ctx->L, ctx->plan.rows);
     if (pairs > ISING_STATIC_SCRATCH_PAIRS) return ISING_ERANGE;
     int64_t* sc = nullptr;
     if (pairs) {
@@ -800,7 +819,11 @@ int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
         case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, series_dev, sc); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, series_dev); break;
         case ISING_PLAN_BANDS:
-            rc = sweep_bands(ctx, n, series_dev, sc, std::min<uint32_t>(kBandChunk, ISING_STATIC_SCRATCH_PAIRS / pairs));
+            if (bands_as_two_pass)
+                rc = sweep_two_pass(ctx, n, series_dev, sc, 1);
+            else
+                rc = sweep_bands(ctx, n, series_dev, sc,
+                                 std::min<uint32_t>(kBandChunk, ISING_STATIC_SCRATCH_PAIRS / pairs));
             break;
         case ISING_PLAN_RESIDENT: {
             BatchItem it;

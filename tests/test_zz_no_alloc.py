@@ -2,7 +2,8 @@
 ising_sweep on identical contexts: the same per-sweep (B, M) and the same
 lattice, for calls of decreasing size in a row (each call reuses the
 library's device array the previous one left its partial sums in), in
-every plan, plus the size limit of that array."""
+every plan, replayed from a captured graph, plus the size limit of that
+array."""
 import numpy as np
 import pytest
 
@@ -70,6 +71,56 @@ def test_static_sweeps_equal_ising_sweep(b):
         finally:
             b.ising_destroy(ref)
             b.ising_destroy(ctx)
+
+
+def test_static_sweeps_replayed_from_a_graph(b):
+    """ising_sweep_static captured into a graph (the callers it is for) and
+    replayed three times from the same start, with the host's own work and
+    synchronisations between replays: every replay's series and lattice
+    equal the same sweeps run eagerly through ising_sweep. A band-plan
+    context is captured as two-pass launches, a fused-plan context as its
+    own launches; ising_sweep itself refuses to be captured on the band
+    plan."""
+    import torch
+    n = 8
+    for L, plan, cw, rows in [(1024, b.ISING_PLAN_BANDS, 1, 4), (2048, b.ISING_PLAN_FUSED, 1, 8)]:
+        G.log(f"static sweeps in a graph L={L} plan={plan}")
+        s = torch.cuda.Stream()
+        ctx = b.ising_create(L, 1.0, 0.05, 2.3, 41, 0.5, stream=s.cuda_stream)
+        ref = b.ising_create(L, 1.0, 0.05, 2.3, 41, 0.5)
+        try:
+            b.ising_plan_set(ctx, plan, cw, rows)
+            b.ising_plan_set(ref, plan, cw, rows)
+            start = b.ising_copy_spins(ctx, L)
+            b.ising_sweep(ref, n)
+            _, B, M = b.ising_observables(ref, b.ISING_OBS_SERIES)
+            want = b.ising_copy_spins(ref, L)
+            series = torch.full((2 * n,), -7, dtype=torch.int64, device="cuda")
+            # one eager call first: the library looks its array up on first use
+            b.ising_sweep_static(ctx, n, series.data_ptr())
+            b.ising_load_spins(ctx, start, 0)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=s):
+                if plan == b.ISING_PLAN_BANDS:
+                    with pytest.raises(b.IsingError) as e:
+                        b.ising_sweep(ctx, 1)
+                    assert e.value.code == b.ISING_EUNSUPPORTED
+                b.ising_sweep_static(ctx, n, series.data_ptr())
+            for rep in range(3):
+                b.ising_load_spins(ctx, start, 0)
+                series.fill_(-7)
+                torch.cuda.synchronize()
+                graph.replay()
+                torch.cuda.synchronize()
+                got = series.cpu().numpy()
+                assert np.array_equal(got[0::2], B), f"L={L} plan={plan} replay {rep}: bond series differ"
+                assert np.array_equal(got[1::2], M), f"L={L} plan={plan} replay {rep}: magnetisation series differ"
+                assert np.array_equal(b.ising_copy_spins(ctx, L), want), f"L={L} plan={plan} replay {rep}: lattices"
+            del graph
+        finally:
+            b.ising_destroy(ctx)
+            b.ising_destroy(ref)
 
 
 def test_static_sweeps_reject_plans_beyond_the_array(b):
