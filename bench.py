@@ -239,7 +239,10 @@ def run_batched(b, torch, stream, count, sweeps, sample, plan=0):
     try:
         plans = {}
         for c, r in zip(ctxs, sub):
-            b.ising_tune(c, 16)  # the side's plan, remembered for later contexts of that side
+            # the side's plan (remembered for later contexts of that side),
+            # from trials long enough that a plan's per-call costs weigh as
+            # little as in the timed 10000-sweep call
+            b.ising_tune(c, 128)
             plans[r.L] = b.ising_plan_info(c)
         torch.cuda.synchronize()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(sub) + 1)]
@@ -385,7 +388,7 @@ def run_fifo(b, rate, count):
     for L in sorted({q.run.L for q in reqs}):
         ctx = b.ising_create(L)
         try:
-            b.ising_tune(ctx, 16)
+            b.ising_tune(ctx, 128)  # trials long enough for per-call costs to weigh as in a request
         finally:
             b.ising_destroy(ctx)
     results = []
