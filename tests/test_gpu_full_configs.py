@@ -59,7 +59,8 @@ def test_served_full_size_requests_equal_solo(b, o):
     """Twelve requests drawn from the served configuration (L up to 2048,
     up to 20000 sweeps) through the continuous-batching server at 1000
     requests/s: each result is bit-identical to the same request run alone;
-    those with L = 64 also equal the oracle."""
+    those with L = 64, and a mid-sized and a largest-side one, also equal
+    the oracle."""
     reqs = W.request_stream(1000.0, count=256)
     pick = sorted(range(256), key=lambda k: reqs[k].run.L)
     chosen = pick[:3] + pick[-3:] + pick[120:126]
@@ -84,3 +85,14 @@ def test_served_full_size_requests_equal_solo(b, o):
             s = o.init(run.L, run.seed, run.p_up)
             Bo, Mo = o.run(s, run.J, run.h, run.T, run.seed, 0, run.sweeps, series=False)
             assert r.lattice_hash == o.fnv1a64(s)
+    # a mid-sized and a largest-side request (the fewest sweeps of each
+    # group, a few seconds of oracle time) against the oracle as well
+    by_rid = {r.rid: r for r in res}
+    for group in (range(6, 12), range(3, 6)):
+        rid = min(group, key=lambda k: sub[k].run.sweeps)
+        run, r = sub[rid].run, by_rid[rid]
+        G.log(f"served request L={run.L} h={run.h} sweeps={run.sweeps} vs oracle")
+        s = o.init(run.L, run.seed, run.p_up)
+        o.run(s, run.J, run.h, run.T, run.seed, 0, run.sweeps, series=False)
+        assert r.lattice_hash == o.fnv1a64(s), f"served L={run.L}: hash differs from the oracle"
+        assert (r.bond_sum, r.mag_sum) == tuple(int(v) for v in o.observables(s)), f"served L={run.L}: (B, M)"
