@@ -353,13 +353,14 @@ def test_batch_stepped_fused_walk_packed_columns_tall_tiles(b, o):
             b.ising_destroy(ctx)
 
 
-def test_batch_stepped_fused_walk_many_large_lattices(b):
+def test_batch_stepped_fused_walk_many_large_lattices(b, o):
     """A stepped batch of 48 lattices of 2048^2 (h = 0 and h = 0.05): tiles
     of fewer rows are used when the batch has too few tiles to fill the GPU
     (this batch sits between the 8-lattice test above and the 1024-lattice
     configuration, which use the shortest and the tallest tiles). Every
-    lattice's series and final lattice equal its own run alone (two-pass
-    plan), over an odd and then an even number of sweeps."""
+    sixth lattice's series and final lattice equal its own run alone
+    (two-pass plan), over an odd and then an even number of sweeps, and the
+    first two (h = 0 and h = 0.05) equal the oracle."""
     runs = [W.Run(L=2048, J=1.0, h=0.05 * (k % 2), T=2.0 + 0.02 * k, seed=100 + k, p_up=0.5, sweeps=3)
             for k in range(48)]
     ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up) for r in runs]
@@ -368,7 +369,12 @@ def test_batch_stepped_fused_walk_many_large_lattices(b):
     b.ising_sweep_batch_plan(ctxs, [2] * 48, b.ISING_BATCH_STEPPED)
     for k, (r, ctx) in enumerate(zip(runs, ctxs)):
         obs, B, M = b.ising_observables(ctx, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+        spins = b.ising_copy_spins(ctx, r.L) if k < 2 else None
         b.ising_destroy(ctx)
+        if k < 2:
+            G.log(f"stepped fused walk: 2048^2 lattice {k} (h={r.h}) vs the oracle")
+            G.assert_same({"spins": spins, "B": B, "M": M, "hash": obs.lattice_hash}, G.oracle_run(o, r, sweeps=5),
+                          f"stepped 2048^2 lattice {k}")
         if k % 6:
             continue
         G.log(f"stepped fused walk: 2048^2 lattice {k} vs its solo run")
