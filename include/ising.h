@@ -324,7 +324,7 @@ int ising_plan_info(const ising_ctx* ctx, uint32_t* plan, uint32_t* chunk_words,
  * ISING_PLAN_BANDS the band height rows >= 1, giving ceil(L / rows) >= 2
  * bands that must all fit the device at once, and cw in {1, 2, 4} rows per
  * wave; 0 picks a default). Switching to the fused plan may allocate a second lattice
- * buffer, to the band plan its edge-row slots and flags. Results do not
+ * buffer, to the band plan its edge-row slots. Results do not
  * depend on the plan.
  * Errors: EUNSUPPORTED if the plan cannot serve the context's L. */
 int ising_plan_set(ising_ctx* ctx, uint32_t plan, uint32_t cw, uint32_t rows);
