@@ -64,7 +64,7 @@ extern "C" {
 
 /* Plan selection (ising_params.flags, low byte). AUTO picks per lattice side:
  * the workgroup-resident kernel for small sides, the band-resident plan for
- * sides 512 to 4096 (about one band of rows per compute unit), the fused
+ * sides 512 to 16384 (about one band of rows per compute unit), the fused
  * one-pass sweep by full-row workgroups where a row fits one workgroup, the
  * fused sweep by wave tiles for larger sides, the two-pass in-place sweep
  * otherwise. The others force a path (ISING_EUNSUPPORTED if the side does
@@ -78,7 +78,7 @@ extern "C" {
 #define ISING_PLAN_BANDS 6u      /* the lattice split into bands of whole rows, one workgroup each, all
                                    * resident at once; each band stays in LDS at one bit per site for
                                    * every sweep of a launch, bands trade edge rows after each half-sweep
-                                   * (L % 8 == 0, L <= 4096) */
+                                   * (L % 8 == 0, L <= 16384) */
 /* Sweeps of one band-plan launch (the lattice crosses HBM once per launch);
  * longer calls are split into launches of this many sweeps. */
 #define ISING_BAND_SWEEPS_PER_LAUNCH 512u

@@ -7,7 +7,8 @@
 // cooperative launch). A workgroup converts its band of both colour planes
 // to bits in LDS (the layout and word update of ising_bits.hpp), runs every
 // half-sweep of the launch there and converts the band back at the end, so
-// the lattice crosses HBM once per launch rather than once per sweep.
+// the lattice crosses HBM once per launch rather than once per sweep. A
+// wave sweeps its rows in chunks of 64 words, a word per lane.
 //
 // A band's first and last rows need the rows just outside it, which belong
 // to the bands above and below. After each half-sweep the wave that updated
@@ -88,7 +89,8 @@ __device__ __forceinline__ void bytes_of_bits(uint32_t* plane, uint32_t i, uint3
     for (uint32_t j = 0; j < 8u && 8u * k + j < Hw; ++j) q[j] = (((v >> (4u * j)) & 0xfu) * 0x00204081u) & 0x01010101u;
 }
 
-template <bool GENERAL>
+// CH: chunks of 64 words a row (Wr <= 64 CH).
+template <bool GENERAL, int CH>
 __global__ __launch_bounds__(1024) void k_bands(BandArgs a) {
     extern __shared__ uint32_t lat[];  // [plane][band row][Wr]
     __shared__ uint32_t red[kBandMaxWaves][2];
@@ -107,13 +109,22 @@ __global__ __launch_bounds__(1024) void k_bands(BandArgs a) {
     }
     __syncthreads();
 
-    const uint32_t k = lane;
-    const bool active = k < Wr;
-    const bool lastw = k + 1u == Wr;
-    const uint32_t valid = lastw ? bl.last_valid : 0xffffffffu;
-    const uint32_t top = lastw ? bl.hb : 31u;
-    const uint32_t kn = lastw ? 0u : k + 1u, kp = k == 0 ? Wr - 1u : k - 1u;
-    const uint32_t top_p = k == 0 ? bl.hb : 31u;
+    // per chunk of 64 words, the lane's word and what its update needs
+    uint32_t kw[CH], valid[CH], top[CH], kn[CH], kp[CH], top_p[CH], kc[CH];
+    bool active[CH];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const uint32_t k = 64u * (uint32_t)ch + lane;
+        const bool lastw = k + 1u == Wr;
+        kw[ch] = k;
+        active[ch] = k < Wr;
+        valid[ch] = lastw ? bl.last_valid : 0xffffffffu;
+        top[ch] = lastw ? bl.hb : 31u;
+        kn[ch] = lastw ? 0u : k + 1u;
+        kp[ch] = k == 0 ? Wr - 1u : k - 1u;
+        top_p[ch] = k == 0 ? bl.hb : 31u;
+        kc[ch] = k < Wr ? k : Wr - 1u;  // lanes past the row poll its last word
+    }
     // rows of this wave: r = wv (mod nw), the band's edge rows first
     const uint32_t nrows = H > wv ? (H - 1u - wv) / nw + 1u : 0u;
     const bool owns_last = (H - 1u) % nw == wv;
@@ -129,47 +140,50 @@ __global__ __launch_bounds__(1024) void k_bands(BandArgs a) {
         const uint64_t* in_slot = a.pub + (size_t)((tau - 1u) & 1u) * slot_words;
         uint64_t* out_slot = a.pub + (size_t)(tau & 1u) * slot_words;
         const uint32_t tag_in = a.base + tau, tag_out = a.base + tau + 1u;
-        const uint32_t kc = active ? k : Wr - 1u;  // lanes past the row poll its last word
         for (uint32_t j = 0; j < nrows; ++j) {
             uint32_t r;
             if (owns_last && wv != 0u) r = j == 0 ? H - 1u : wv + (j - 1u) * nw;
             else if (owns_last && H > 1u) r = j == 0 ? 0u : j == 1u ? H - 1u : (j - 1u) * nw;
             else r = wv + j * nw;
             const uint32_t i = r0 + r;
-            uint32_t U = 0, D = 0;
-            if (r == 0) {
-                if (tau == 0) {
-                    if (active) U = bits_of_bytes(oth_g, i == 0 ? L - 1u : i - 1u, k, Hw);
-                } else {
-                    U = take_word(in_slot + (2u * gu + 1u) * Wr + kc, tag_in, a.err);
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch) {
+                const uint32_t k = kw[ch];
+                uint32_t U = 0, D = 0;
+                if (r == 0) {
+                    if (tau == 0) {
+                        if (active[ch]) U = bits_of_bytes(oth_g, i == 0 ? L - 1u : i - 1u, k, Hw);
+                    } else {
+                        U = take_word(in_slot + (2u * gu + 1u) * Wr + kc[ch], tag_in, a.err);
+                    }
+                } else if (active[ch]) {
+                    U = oth_p[(r - 1u) * Wr + k];
                 }
-            } else if (active) {
-                U = oth_p[(r - 1u) * Wr + k];
-            }
-            if (r == H - 1u) {
-                if (tau == 0) {
-                    if (active) D = bits_of_bytes(oth_g, i + 1u == L ? 0u : i + 1u, k, Hw);
-                } else {
-                    D = take_word(in_slot + 2u * gd * Wr + kc, tag_in, a.err);
+                if (r == H - 1u) {
+                    if (tau == 0) {
+                        if (active[ch]) D = bits_of_bytes(oth_g, i + 1u == L ? 0u : i + 1u, k, Hw);
+                    } else {
+                        D = take_word(in_slot + 2u * gd * Wr + kc[ch], tag_in, a.err);
+                    }
+                } else if (active[ch]) {
+                    D = oth_p[(r + 1u) * Wr + k];
                 }
-            } else if (active) {
-                D = oth_p[(r + 1u) * Wr + k];
-            }
-            if (active) {
-                const uint32_t own = own_p[r * Wr + k];
-                const uint32_t O = oth_p[r * Wr + k], On = oth_p[r * Wr + kn], Op = oth_p[r * Wr + kp];
-                const uint32_t S = bits_same_row(O, On, Op, top, top_p, valid, (i + c) & 1u);
-                const uint32_t reject = bits_reject<GENERAL>(bl, own, U, D, O, S, i * Hw + 8u * k, t, c, a.k0, a.k1);
-                const uint32_t nwd = own ^ (valid & ~reject);
-                own_p[r * Wr + k] = nwd;
-                if (r == 0) put_word(out_slot + 2u * g * Wr + k, tag_out, nwd);
-                if (r == H - 1u) put_word(out_slot + (2u * g + 1u) * Wr + k, tag_out, nwd);
-                if (c) {
-                    // bonds of this colour-1 word, all final now, that disagree
-                    mis += __builtin_popcount(nwd ^ U) + __builtin_popcount(nwd ^ D) +
-                           __builtin_popcount(nwd ^ O) + __builtin_popcount(nwd ^ S);
+                if (active[ch]) {
+                    const uint32_t own = own_p[r * Wr + k];
+                    const uint32_t O = oth_p[r * Wr + k], On = oth_p[r * Wr + kn[ch]], Op = oth_p[r * Wr + kp[ch]];
+                    const uint32_t S = bits_same_row(O, On, Op, top[ch], top_p[ch], valid[ch], (i + c) & 1u);
+                    const uint32_t reject = bits_reject<GENERAL>(bl, own, U, D, O, S, i * Hw + 8u * k, t, c, a.k0, a.k1);
+                    const uint32_t nwd = own ^ (valid[ch] & ~reject);
+                    own_p[r * Wr + k] = nwd;
+                    if (r == 0) put_word(out_slot + 2u * g * Wr + k, tag_out, nwd);
+                    if (r == H - 1u) put_word(out_slot + (2u * g + 1u) * Wr + k, tag_out, nwd);
+                    if (c) {
+                        // bonds of this colour-1 word, all final now, that disagree
+                        mis += __builtin_popcount(nwd ^ U) + __builtin_popcount(nwd ^ D) +
+                               __builtin_popcount(nwd ^ O) + __builtin_popcount(nwd ^ S);
+                    }
+                    ups += __builtin_popcount(nwd);
                 }
-                ups += __builtin_popcount(nwd);
             }
         }
         if (c) {
@@ -206,6 +220,12 @@ __global__ __launch_bounds__(1024) void k_bands(BandArgs a) {
     }
 }
 
+// Dynamic LDS beyond the default 64 KiB has to be allowed per kernel.
+hipError_t allow_lds(const void* kernel, uint32_t bytes) {
+    if (bytes <= 65536u) return hipSuccess;
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 __global__ __launch_bounds__(256) void k_bands_clear(uint64_t* pub, size_t words) {
     for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (size_t)gridDim.x * blockDim.x)
         pub[w] = 0;
@@ -216,19 +236,34 @@ __global__ __launch_bounds__(256) void k_bands_reduce(const int64_t* part, uint3
     reduce_partials(PartialReduce{part + 2ull * s * G, G, ser + 2ull * s});
 }
 
-const void* bands_kernel(bool general) {
-    return general ? reinterpret_cast<const void*>(&k_bands<true>) : reinterpret_cast<const void*>(&k_bands<false>);
+template <bool GENERAL>
+const void* bands_kernel_t(uint32_t chunks) {
+    switch (chunks) {
+        case 1: return reinterpret_cast<const void*>(&k_bands<GENERAL, 1>);
+        case 2: return reinterpret_cast<const void*>(&k_bands<GENERAL, 2>);
+        case 3: return reinterpret_cast<const void*>(&k_bands<GENERAL, 3>);
+        default: return reinterpret_cast<const void*>(&k_bands<GENERAL, 4>);
+    }
+}
+
+const void* bands_kernel(bool general, uint32_t Wr) {
+    const uint32_t chunks = (Wr + 63u) / 64u;
+    return general ? bands_kernel_t<true>(chunks) : bands_kernel_t<false>(chunks);
 }
 
 }  // namespace
 
-uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general) {
+uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general, uint32_t Wr) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bands_kernel(general), (int)threads, lds_bytes) !=
-        hipSuccess)
+    if (Wr == 0 || Wr > kBandMaxWr) return 0;
+    const void* k = bands_kernel(general, Wr);
+    if (allow_lds(k, lds_bytes) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, (int)threads, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
         return 0;
+    }
     return (uint32_t)(per > 0 ? per : 0) * (uint32_t)cus;
 }
 
@@ -238,8 +273,11 @@ hipError_t launch_bands(const BandArgs& a, uint32_t G, uint32_t threads, hipStre
         return hipErrorInvalidValue;
     BandArgs arg = a;
     void* args[] = {&arg};
-    return hipLaunchCooperativeKernel(bands_kernel(a.general != 0), dim3(G), dim3(threads), args,
-                                      band_lds_bytes(a.L, G, a.Wr), s);
+    const uint32_t lds = band_lds_bytes(a.L, G, a.Wr);
+    const void* k = bands_kernel(a.general != 0, a.Wr);
+    const hipError_t e = allow_lds(k, lds);
+    if (e != hipSuccess) return e;
+    return hipLaunchCooperativeKernel(k, dim3(G), dim3(threads), args, lds, s);
 }
 
 hipError_t launch_bands_clear(uint64_t* pub, size_t words, hipStream_t s) {

@@ -25,16 +25,17 @@ struct BandArgs {
     BitsLattice bl;
 };
 
-// Bands need a row to fit one wave (Wr <= 64) and every band to hold at
-// least one row.
-constexpr uint32_t kBandMaxWr = 64;
+// A wave sweeps a band row in chunks of 64 words (a word per lane); rows of
+// up to 256 words (sides up to 16384), and every band holds at least one
+// row.
+constexpr uint32_t kBandMaxWr = 256;
 // Tagged edge-row words a band launch uses (64-bit: tag << 32 | bit word).
 inline size_t band_pub_words(uint32_t G, uint32_t Wr) { return (size_t)2 * G * 2 * Wr; }
 inline uint32_t band_lds_bytes(uint32_t L, uint32_t G, uint32_t Wr) { return 2u * ((L + G - 1u) / G) * Wr * 4u; }
 
 // Workgroups of `threads` threads that can be resident at once for bands of
-// lds_bytes each (0 on error).
-uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general);
+// lds_bytes each and rows of Wr words (0 on error).
+uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general, uint32_t Wr);
 // One cooperative launch of G band workgroups of `threads` threads.
 hipError_t launch_bands(const BandArgs& a, uint32_t G, uint32_t threads, hipStream_t s);
 // Zero `words` tagged edge words (before tags restart from 0).

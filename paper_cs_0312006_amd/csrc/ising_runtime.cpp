@@ -84,9 +84,9 @@ constexpr float kTuneMargin = 0.03f;
 // Band plan: sides it serves by default, and sweeps per launch (the
 // partials of a launch are bands x sweeps pairs). Its default band height
 // gives about one band per compute unit: one band a CU measured fastest
-// from 512 to 4096 (fewer bands leave CUs idle, more put unequal numbers of
-// bands on CUs, and each band's half-sweep is bound by the latency of its
-// own rows and of the edge exchange, not by the chip's throughput).
+// from 512 to 16384 (fewer bands leave CUs idle, more put unequal numbers of
+// bands on CUs; at the small sides a band's half-sweep is bound by the
+// latency of its rows and of the edge exchange, not by the chip's rate).
 constexpr uint32_t kBandMinDefaultL = 512;
 constexpr uint32_t kBandChunk = ISING_BAND_SWEEPS_PER_LAUNCH;
 constexpr uint32_t kTuneRounds = 3;
@@ -169,7 +169,8 @@ uint32_t band_words(uint32_t L) { return (L / 8u + 7u) / 8u; }
 static bool bands_fit(uint32_t L, uint32_t rows, uint32_t per_wave) {
     const uint32_t G = band_count(L, rows);
     if (G < 2u || G > L) return false;
-    const uint32_t cap = bands_capacity(band_threads(L, G, per_wave), band_lds_bytes(L, G, band_words(L)), true);
+    const uint32_t cap =
+        bands_capacity(band_threads(L, G, per_wave), band_lds_bytes(L, G, band_words(L)), true, band_words(L));
     return cap >= G;
 }
 

@@ -62,6 +62,9 @@ CASES = [
     (4096, 1.0, 0.0, 2.269185, 0.5, 7, 16, 2, [5, 7]),
     (4096, 1.0, 0.1, 1.5, 0.5, 17, 8, 1, [6, 6]),
     (4096, 1.0, 0.0, 1e300, 0.5, 18, 4, 1, [3]),          # every proposal accepted
+    (4104, 1.0, 0.1, 2.0, 0.5, 20, 17, 1, [3, 2]),        # 65-word rows (a second chunk of one word), 17-row bands
+    (8192, 1.0, 0.0, 2.269185, 0.5, 21, 32, 1, [2, 3]),   # two chunks a row, two rows a wave
+    (16384, -1.0, 0.05, 2.5, 0.5, 22, 64, 1, [2, 1]),     # four chunks a row, 128 KiB of LDS a band
 ]
 
 
@@ -121,20 +124,17 @@ def test_bands_after_batched_sweeps(b, o):
 
 
 def test_band_plan_limits(b):
-    """Sides whose rows do not fit one wave, or heights leaving fewer than
-    two bands, are refused; the context keeps its plan."""
-    ctx = b.ising_create(8192, 1.0, 0.0, 2.269185, 1, 0.5)
-    try:
-        before = b.ising_plan_info(ctx)
-        with pytest.raises(b.IsingError) as e:
-            b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, 16)
-        assert e.value.code == b.ISING_EUNSUPPORTED
-        assert b.ising_plan_info(ctx) == before
-    finally:
-        b.ising_destroy(ctx)
-    ctx = b.ising_create(64, 1.0, 0.0, 2.269185, 1, 0.5)
-    try:
-        with pytest.raises(b.IsingError):
-            b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, 64)
-    finally:
-        b.ising_destroy(ctx)
+    """Sides whose rows are wider than 256 words (32768: 512), band heights
+    that need more bands than can be resident at once (8192 with 16-row
+    bands: 512), and heights that leave fewer than two bands are refused;
+    the context keeps its plan."""
+    for L, rows in ((32768, 128), (8192, 16), (64, 64)):
+        ctx = b.ising_create(L, 1.0, 0.0, 2.269185, 1, 0.5)
+        try:
+            before = b.ising_plan_info(ctx)
+            with pytest.raises(b.IsingError) as e:
+                b.ising_plan_set(ctx, b.ISING_PLAN_BANDS, 0, rows)
+            assert e.value.code == b.ISING_EUNSUPPORTED, (L, rows)
+            assert b.ising_plan_info(ctx) == before
+        finally:
+            b.ising_destroy(ctx)
