@@ -748,7 +748,7 @@ def main():
         "roofline_alu": roof_alu,
         "host_wall_s": head["host_s"],
         # the paper's own figures, as context only (another machine, another
-        # metric): its fragment-program Ising sweep on an NV30 (Section 4)
+        # metric): its fragment-program Ising sweep on an NV30 (Section 5)
         "paper_context": {"nv30_gflops": 7.0, "nv30_fraction_of_peak": 0.44,
                           "site_visits_per_ns_table4": [0.004, 0.01],
                           "note": "context only, not a baseline for this metric"},
