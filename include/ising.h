@@ -222,7 +222,11 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * and runs all of their sweeps from its local memory, or, when that is
  * predicted slower, graph replays of passes that spread every lattice over
  * the whole GPU. The descriptors are staged through pinned host
- * memory by one copy kernel. Lattices may differ in L, J, h, T and seed;
+ * memory by one copy kernel. A batch with a single lattice to sweep whose
+ * side the band-resident plan serves by default (512 to 16384) runs on that
+ * plan instead, on the context's stream ordered after `stream`'s earlier
+ * work and before its later work (neither batch plan can spread one lattice
+ * over the chip). Lattices may differ in L, J, h, T and seed;
  * each must satisfy L % 8 == 0 and have no pending device error. Contexts
  * are validated before anything is launched (all-or-nothing). The results
  * are bit-identical to calling ising_sweep on each context alone.
@@ -299,10 +303,12 @@ typedef struct ising_batch_rate {
  * sweep. Host only. */
 int ising_batch_rates(int device, ising_batch_rate* out, size_t n, int* tuned, double* floor_ns);
 
-/* The plan ISING_BATCH_AUTO would run for this batch (ISING_BATCH_RESIDENT
- * or ISING_BATCH_STEPPED), the stepped tile height (0 when the stepped plan
- * would not use the one-pass walk), and predicted_ns[0], [1] (optional):
- * the predicted resident and stepped times. Host only. */
+/* The batch plan ISING_BATCH_AUTO's model picks for this batch
+ * (ISING_BATCH_RESIDENT or ISING_BATCH_STEPPED), the stepped tile height (0
+ * when the stepped plan would not use the one-pass walk), and
+ * predicted_ns[0], [1] (optional): the predicted resident and stepped
+ * times. (A batch with a single lattice to sweep that the band plan serves
+ * runs on that plan; see ising_sweep_batch.) Host only. */
 int ising_batch_choice(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, uint32_t* plan,
                        uint32_t* rows, double* predicted_ns);
 

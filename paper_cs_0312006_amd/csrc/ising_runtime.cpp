@@ -324,6 +324,36 @@ int ctx_reserve_series(ising_ctx* ctx, uint64_t more) {
     return ISING_OK;
 }
 
+// The band plan's edge-row slots for G bands and its timeout mark (the
+// slots only grow; growing waits for the launches that may still use them).
+static int ctx_band_slots(ising_ctx* ctx, uint32_t G) {
+    if (G > ctx->band_cap) {
+        if (ctx->band_cap) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->band_pub) (void)hipFree(ctx->band_pub);
+        ctx->band_pub = nullptr;
+        ctx->band_cap = 0;
+        const size_t words = band_pub_words(G, band_words(ctx->L));
+        if (hipMalloc(&ctx->band_pub, words * sizeof(uint64_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            return ISING_ENOMEM;
+        }
+        // fresh slots carry tag 0, below every tag a launch waits for
+        HIP_TRY(ctx, hipMemsetAsync(ctx->band_pub, 0, words * sizeof(uint64_t), ctx->stream));
+        ctx->band_base = 0;
+        ctx->band_cap = G;
+    }
+    if (!ctx->band_err) {
+        if (hipMalloc(&ctx->band_err, sizeof(uint32_t)) != hipSuccess ||
+            hipHostMalloc(&ctx->band_err_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return ISING_ENOMEM;
+        }
+        *ctx->band_err_host = 0;
+        HIP_TRY(ctx, hipMemsetAsync(ctx->band_err, 0, sizeof(uint32_t), ctx->stream));
+    }
+    return ISING_OK;
+}
+
 // Allocate what the context's plan needs: the second lattice buffer for
 // ping-pong, partial-sum buffers sized to the plan's tiles or blocks.
 int ctx_prepare_plan(ising_ctx* ctx) {
@@ -337,32 +367,8 @@ int ctx_prepare_plan(ising_ctx* ctx) {
         ctx->owns_buf[1] = true;
     }
     if (ctx->plan.kind == ISING_PLAN_BANDS) {
-        const uint32_t G = band_count(ctx->L, ctx->plan.rows);
-        if (G > ctx->band_cap) {
-            // earlier launches may still use the old slots and flags
-            if (ctx->band_cap) HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-            if (ctx->band_pub) (void)hipFree(ctx->band_pub);
-            ctx->band_pub = nullptr;
-            ctx->band_cap = 0;
-            const size_t words = band_pub_words(G, band_words(ctx->L));
-            if (hipMalloc(&ctx->band_pub, words * sizeof(uint64_t)) != hipSuccess) {
-                (void)hipGetLastError();
-                return ISING_ENOMEM;
-            }
-            // fresh slots carry tag 0, below every tag a launch waits for
-            HIP_TRY(ctx, hipMemsetAsync(ctx->band_pub, 0, words * sizeof(uint64_t), ctx->stream));
-            ctx->band_base = 0;
-            ctx->band_cap = G;
-        }
-        if (!ctx->band_err) {
-            if (hipMalloc(&ctx->band_err, sizeof(uint32_t)) != hipSuccess ||
-                hipHostMalloc(&ctx->band_err_host, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                return ISING_ENOMEM;
-            }
-            *ctx->band_err_host = 0;
-            HIP_TRY(ctx, hipMemsetAsync(ctx->band_err, 0, sizeof(uint32_t), ctx->stream));
-        }
+        const int rc = ctx_band_slots(ctx, band_count(ctx->L, ctx->plan.rows));
+        if (rc != ISING_OK) return rc;
     }
     uint32_t need = 0;
     const Planes pl = ctx_planes(ctx);
@@ -422,8 +428,7 @@ static int sweep_fused(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part0,
 // The band plan's partials for launches of kBandChunk sweeps, allocated on
 // the first ising_sweep (a context that only runs in batches never needs
 // them, and ising_sweep_static uses the library's array instead).
-static int ctx_band_part(ising_ctx* ctx) {
-    const uint32_t G = band_count(ctx->L, ctx->plan.rows);
+static int ctx_band_part(ising_ctx* ctx, uint32_t G) {
     if (ctx->band_part && ctx->band_part_cap >= G) return ISING_OK;
     if (ctx->band_part) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -440,10 +445,12 @@ static int ctx_band_part(ising_ctx* ctx) {
     return ISING_OK;
 }
 
-// n sweeps of the band plan: launches of up to `chunk` sweeps, each
-// followed by the sum of its bands' partials (at part) into ser.
-static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, uint32_t chunk) {
-    const uint32_t L = ctx->L, G = band_count(L, ctx->plan.rows);
+// n sweeps of the band plan with bands of `rows` rows, `per_wave` rows a
+// wave: launches of up to `chunk` sweeps, each followed by the sum of its
+// bands' partials (at part) into ser.
+static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, uint32_t chunk, uint32_t rows,
+                       uint32_t per_wave) {
+    const uint32_t L = ctx->L, G = band_count(L, rows);
     const Planes pl = ctx_planes(ctx);
     const uint32_t mode = bits_mode(ctx->table);
     BandArgs a{};
@@ -469,7 +476,7 @@ static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, 
         a.t0 = (uint32_t)(ctx->t + done);
         a.n = m;
         a.base = ctx->band_base;
-        HIP_TRY(ctx, launch_bands(a, G, band_threads(L, G, ctx->plan.cw), ctx->stream));
+        HIP_TRY(ctx, launch_bands(a, G, band_threads(L, G, per_wave), ctx->stream));
         // every slot the launch used ends it tagged base + 2 m or base + 2 m - 1
         ctx->band_base += 2u * m;
         HIP_TRY(ctx, launch_bands_reduce(part, G, m, ser + 2 * done, ctx->stream));
@@ -754,8 +761,8 @@ int ising_sweep(ising_ctx* ctx, uint64_t n) {
         case ISING_PLAN_TWO_PASS: rc = sweep_two_pass(ctx, n, ser, ctx->part[0]); break;
         case ISING_PLAN_GENERIC: rc = sweep_generic(ctx, n, ser); break;
         case ISING_PLAN_BANDS:
-            rc = ctx_band_part(ctx);
-            if (rc == ISING_OK) rc = sweep_bands(ctx, n, ser, ctx->band_part, kBandChunk);
+            rc = ctx_band_part(ctx, band_count(ctx->L, ctx->plan.rows));
+            if (rc == ISING_OK) rc = sweep_bands(ctx, n, ser, ctx->band_part, kBandChunk, ctx->plan.rows, ctx->plan.cw);
             break;
         default: return ISING_EUNSUPPORTED;
     }
@@ -824,7 +831,8 @@ int ising_sweep_static(ising_ctx* ctx, uint64_t n, int64_t* series_dev) {
                 rc = sweep_two_pass(ctx, n, series_dev, sc, 1);
             else
                 rc = sweep_bands(ctx, n, series_dev, sc,
-                                 std::min<uint32_t>(kBandChunk, ISING_STATIC_SCRATCH_PAIRS / pairs));
+                                 std::min<uint32_t>(kBandChunk, ISING_STATIC_SCRATCH_PAIRS / pairs), ctx->plan.rows,
+                                 ctx->plan.cw);
             break;
         case ISING_PLAN_RESIDENT: {
             BatchItem it;
@@ -846,6 +854,52 @@ int ising_sweep_batch(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t c
     return ising_sweep_batch_plan(ctxs, n_sweeps, count, stream, ISING_BATCH_AUTO);
 }
 
+// A batch with one lattice to sweep: the batch plans spread it over too
+// few workgroups (the resident plan: one; the stepped plan: one wave per
+// tile), so it runs on the band plan at its default band height (whatever
+// the context's own plan), ordered like a batch on stream s: after s's
+// earlier work and before its later work (s null: the context's stream,
+// which every earlier batch of the engine was ordered before).
+static int lone_band_batch(ising_ctx* ctx, uint64_t n, hipStream_t s) {
+    int rc = ctx_enter(ctx);  // the engine orders this context afresh next time
+    if (rc != ISING_OK) return rc;
+    Plan bp;
+    if (!plan_for(ctx->L, ISING_PLAN_BANDS, 0, 0, &bp)) return ISING_EUNSUPPORTED;
+    const uint32_t G = band_count(ctx->L, bp.rows);
+    if ((rc = ctx_reserve_series(ctx, n)) != ISING_OK) return rc;
+    if ((rc = ctx_band_slots(ctx, G)) != ISING_OK) return rc;
+    if ((rc = ctx_band_part(ctx, G)) != ISING_OK) return rc;
+    const bool other = s && s != ctx->stream;
+    struct Ev {
+        hipEvent_t e = nullptr;
+        ~Ev() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    } ev;
+    if (other) {
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventRecord(ev.e, s));
+        HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ev.e, 0));
+    }
+    ++ctx->gen;
+    rc = sweep_bands(ctx, n, ctx->series + 2 * ctx->series_len, ctx->band_part, kBandChunk, bp.rows, bp.cw);
+    if (rc != ISING_OK) return rc;
+    ctx->t += n;
+    ctx->series_len += n;
+    if (other) {
+        HIP_TRY(ctx, hipEventRecord(ev.e, ctx->stream));
+        HIP_TRY(ctx, hipStreamWaitEvent(s, ev.e, 0));
+    }
+    return ISING_OK;
+}
+
+// Whether a batch of one lattice with sweeps goes to lone_band_batch: the
+// sides where the band plan is the single-lattice default.
+static bool lone_band_fits(const ising_ctx* c) {
+    Plan bp;
+    return c->L >= kBandMinDefaultL && plan_for(c->L, ISING_PLAN_BANDS, 0, 0, &bp);
+}
+
 int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, size_t count, void* stream,
                            uint32_t plan) {
     if (!ctxs || !n_sweeps || plan > ISING_BATCH_STEPPED) return ISING_EINVAL;
@@ -863,6 +917,17 @@ int ising_sweep_batch_plan(ising_ctx* const* ctxs, const uint64_t* n_sweeps, siz
             if (ctxs[j] == c) return ISING_EINVAL;  // one context may appear once
     }
     if (hipSetDevice(dev) != hipSuccess) return ISING_EDEVICE;
+    if (plan == ISING_BATCH_AUTO) {
+        size_t live = 0, only = 0;
+        for (size_t k = 0; k < count; ++k)
+            if (n_sweeps[k]) {
+                ++live;
+                only = k;
+            }
+        if (live == 0) return ISING_OK;
+        if (live == 1 && lone_band_fits(ctxs[only]))
+            return lone_band_batch(ctxs[only], n_sweeps[only], static_cast<hipStream_t>(stream));
+    }
     // the plan (AUTO) and the stepped tile height predicted fastest from
     // the device's per-class rates
     BatchChoice ch;

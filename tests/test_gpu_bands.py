@@ -138,3 +138,32 @@ def test_band_plan_limits(b):
             assert b.ising_plan_info(ctx) == before
         finally:
             b.ising_destroy(ctx)
+
+
+def test_single_lattice_batches_run_on_bands(b, o):
+    """ISING_BATCH_AUTO with one lattice to sweep (sides the band plan
+    serves; other contexts of the batch with no sweeps): the band plan runs
+    it, on an explicit stream or the library's, in order with the batches
+    before and after that include the same context, and every context
+    equals the oracle."""
+    import torch
+    runs = [W.Run(L=512, h=0.05, T=2.3, seed=51, sweeps=14), W.Run(L=1088, T=2.5, seed=52, sweeps=14),
+            W.Run(L=64, seed=53, sweeps=14)]
+    ctxs = [b.ising_create(r.L, r.J, r.h, r.T, r.seed, r.p_up, b.ISING_PLAN_TWO_PASS) for r in runs]
+    s = torch.cuda.Stream()
+    try:
+        G.log("batch of three, then single-lattice batches, then a batch of three")
+        b.ising_sweep_batch_plan(ctxs, [3, 3, 3], b.ISING_BATCH_AUTO)
+        b.ising_sweep_batch_plan(ctxs, [5, 0, 0], b.ISING_BATCH_AUTO, stream=s.cuda_stream)
+        b.ising_sweep_batch_plan(ctxs, [0, 5, 0], b.ISING_BATCH_AUTO)
+        b.ising_sweep_batch_plan(ctxs, [0, 0, 5], b.ISING_BATCH_AUTO)  # 64: a batch plan
+        b.ising_sweep_batch_plan(ctxs, [6, 6, 6], b.ISING_BATCH_AUTO, stream=s.cuda_stream)
+        torch.cuda.synchronize()
+        for r, c in zip(runs, ctxs):
+            assert b.ising_plan_info(c)[0] == b.ISING_PLAN_TWO_PASS  # the context's own plan is kept
+            obs, B, M = b.ising_observables(c, b.ISING_OBS_SERIES | b.ISING_OBS_HASH)
+            got = {"spins": b.ising_copy_spins(c, r.L), "B": B, "M": M, "hash": obs.lattice_hash}
+            G.assert_same(got, G.oracle_run(o, r), f"single-lattice batches L={r.L}")
+    finally:
+        for c in ctxs:
+            b.ising_destroy(c)
