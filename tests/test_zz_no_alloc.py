@@ -60,6 +60,7 @@ def test_static_sweeps_equal_ising_sweep(b):
         (4096, b.ISING_PLAN_BANDS, 0, 16, 1.0, 0.0, 2.269185, 12, 10),
         # 256 one-row bands: 256 pairs a sweep, launches of 256 sweeps
         (256, b.ISING_PLAN_BANDS, 0, 1, 1.0, 0.1, 2.0, 13, 600),
+        (8192, b.ISING_PLAN_BANDS, 0, 32, -1.0, 0.05, 2.5, 14, 6),  # rows of two 64-word chunks
     ]
     for L, plan, cw, rows, J, h, T, seed, n in cases:
         G.log(f"static scratch L={L} plan={plan}")
