@@ -64,7 +64,7 @@ extern "C" {
 
 /* Plan selection (ising_params.flags, low byte). AUTO picks per lattice side:
  * the workgroup-resident kernel for small sides, the band-resident plan for
- * sides 512 to 16384 (about one band of rows per compute unit), the fused
+ * sides 192 to 16384 (about one band of rows per compute unit), the fused
  * one-pass sweep by full-row workgroups where a row fits one workgroup, the
  * fused sweep by wave tiles for larger sides, the two-pass in-place sweep
  * otherwise. The others force a path (ISING_EUNSUPPORTED if the side does
@@ -223,7 +223,7 @@ int ising_load_spins(ising_ctx* ctx, const int8_t* host, size_t n, uint64_t t);
  * predicted slower, graph replays of passes that spread every lattice over
  * the whole GPU. The descriptors are staged through pinned host
  * memory by one copy kernel. A batch with a single lattice to sweep whose
- * side the band-resident plan serves by default (512 to 16384) runs on that
+ * side the band-resident plan serves by default (192 to 16384) runs on that
  * plan instead, on the context's stream ordered after `stream`'s earlier
  * work and before its later work (neither batch plan can spread one lattice
  * over the chip). Lattices may differ in L, J, h, T and seed;

@@ -84,10 +84,10 @@ constexpr float kTuneMargin = 0.03f;
 // Band plan: sides it serves by default, and sweeps per launch (the
 // partials of a launch are bands x sweeps pairs). Its default band height
 // gives about one band per compute unit: one band a CU measured fastest
-// from 512 to 16384 (fewer bands leave CUs idle, more put unequal numbers of
+// from 192 to 16384 (fewer bands leave CUs idle, more put unequal numbers of
 // bands on CUs; at the small sides a band's half-sweep is bound by the
 // latency of its rows and of the edge exchange, not by the chip's rate).
-constexpr uint32_t kBandMinDefaultL = 512;
+constexpr uint32_t kBandMinDefaultL = 192;
 constexpr uint32_t kBandChunk = ISING_BAND_SWEEPS_PER_LAUNCH;
 constexpr uint32_t kTuneRounds = 3;
 
