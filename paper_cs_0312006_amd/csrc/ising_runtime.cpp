@@ -572,7 +572,7 @@ static int sweep_replays(ising_ctx* ctx, uint64_t n, uint64_t* left) {
     *left = n;
     const uint64_t reps = n / kGraphSweeps;
     if (reps == 0 || ctx->plan.kind != ISING_PLAN_TWO_PASS) return ISING_OK;
-    if (ctx->gexec && ctx->gcur != ctx->cur) ctx_drop_graphs(ctx);  // a fused batch or Creutz sweep moved the lattice
+    if (ctx->gexec && ctx->gcur != (uint32_t)ctx->cur) ctx_drop_graphs(ctx);  // a fused batch or Creutz sweep moved the lattice
     if (!ctx->gexec) {
         const int rc = ctx_build_graph(ctx);
         if (rc != ISING_OK) return rc;
