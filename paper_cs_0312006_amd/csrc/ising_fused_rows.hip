@@ -135,6 +135,9 @@ __global__ void __launch_bounds__(1024, 4) k_fused_rows(FusedArgs a, AcceptTable
             // slots of rows i-1 and i, which this step no longer reads
             c1[(u + 3) & 3] = ld<CW>(rs1, xb, rbyte(i + 3));
             c0o[u & 1] = ld<CW>(rs0, xb, rbyte(i + 2));
+            // issued here, a whole step before their use (the scheduler would
+            // otherwise sink them to the middle of the step)
+            __builtin_amdgcn_sched_barrier(0);
             constexpr int P = (u & 1) == 0 ? 1 : 0;  // i even: both updates have same-row side P = 1
             const uint32_t e1 = edge(rd, P, 2u);  // old colour-1 row i+1
             const uint32_t e0 = edge(rd, P, 0u);  // new colour-0 row i
