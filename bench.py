@@ -33,12 +33,18 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (32-bit op
 # copy in the same runs reads 524300 KiB of FETCH_SIZE and writes 1048576
 # KiB of WRITE_SIZE. VALU lane-ops are SQ_INSTS_VALU x 64; VALU busy is
 # SQ_ACTIVE_INST_VALU / 256 compute units / (GRBM_GUI_ACTIVE / 8 XCDs).
-PROFILED_SOURCES = "5e1d18355bda76c9"
+PROFILED_SOURCES = "aaf5cc389756ada4"
 PROFILED = {
-    # profiles/k_fused_rows_ising2d_32768.md, mean of 140 dispatches
-    "k_fused_rows<4,128>": {"hbm_bytes_per_launch": (540867.7 * 2.0 + 1048580.0) * 1024,
-                            "valu_lane_ops_per_attempt": 232145300.4 * 64 / 2 ** 30,
-                            "valu_busy_rocprof": 0.829},
+    # profiles/k_fused_rows_ising2d_32768.md: FETCH/WRITE means of 140
+    # dispatches, VALU counters of the 35 in the counter pass
+    "k_fused_rows<4,128>": {"hbm_bytes_per_launch": (532789.7 * 2.0 + 1048621.0) * 1024,
+                            "valu_lane_ops_per_attempt": 231620842.4 * 64 / 2 ** 30,
+                            "valu_busy_rocprof": 0.845},
+    # the wave-tile shape the autotuner takes when it beats the full rows by
+    # more than its margin (same passes: 27 dispatches for bytes, 132 for VALU)
+    "k_fused<4,32>": {"hbm_bytes_per_launch": (647856.8 * 2.0 + 1048835.0) * 1024,
+                      "valu_lane_ops_per_attempt": 227870305.6 * 64 / 2 ** 30,
+                      "valu_busy_rocprof": 0.842},
 }
 
 
@@ -58,11 +64,11 @@ PROFILED_BATCH = {"kernel": "k_batch (bit-packed lattices in workgroup memory)",
                   "valu_lane_ops_per_attempt": 192905902547.0 * 64 / (388630784 * 2000),
                   "valu_busy_rocprof": 0.932}
 MULTI_FUSED_FILES = ("ising_multi_fused.hip", "ising_fused_core.hpp", "ising_device.hpp", "ising_launch.hpp")
-PROFILED_MULTI_FUSED_SOURCES = "3e199830c7ada852"
+PROFILED_MULTI_FUSED_SOURCES = "562f1a3a50200cd3"
 PROFILED_MULTI_FUSED = {"kernel": "k_multi_fused (one launch per sweep)",
-                        "valu_lane_ops_per_attempt": 131548509.0 * 64 / 388630784,
-                        "valu_busy_rocprof": 0.877,
-                        "hbm_bytes_per_sweep": (287353.4 * 2.0 + 386280.7) * 1024}
+                        "valu_lane_ops_per_attempt": 131454301.0 * 64 / 388630784,
+                        "valu_busy_rocprof": 0.887,
+                        "hbm_bytes_per_sweep": (244661.1 * 2.0 + 412989.1) * 1024}
 
 
 def batched_roofline(res, stepped):
