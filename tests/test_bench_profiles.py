@@ -41,3 +41,12 @@ def test_profile_summaries_exist():
                  "k_multi_fused_served_stream.md", "k_vec_micro.md", "k_perc_relax_percolation_32768.md",
                  "k_bands_ising2d_4096.md"):
         assert os.path.isfile(os.path.join(ROOT, "profiles", name)), name
+
+
+def test_recorded_profiles_belong_to_the_committed_kernels():
+    # every figure bench.py prices was taken on the kernels as they are now:
+    # a kernel source change without a new profile fails here
+    assert bench.kernel_sources_hash() == bench.PROFILED_SOURCES
+    assert bench.kernel_sources_hash(bench.CREUTZ_FILES) == bench.PROFILED_CREUTZ_SOURCES
+    assert bench.kernel_sources_hash(bench.BATCH_FILES) == bench.PROFILED_BATCH_SOURCES
+    assert bench.kernel_sources_hash(bench.MULTI_FUSED_FILES) == bench.PROFILED_MULTI_FUSED_SOURCES
