@@ -23,6 +23,7 @@ struct BandArgs {
     uint32_t* err;      // set when a wait for a neighbour gives up
     uint32_t general;   // 1: the (s, m) classes (h != 0), 0: the two h = 0 classes
     BitsLattice bl;
+    AcceptTable at;     // the acceptance table (byte-resident bands)
 };
 
 // A wave sweeps a band row in chunks of 64 words (a word per lane); rows of
@@ -36,7 +37,9 @@ inline uint32_t band_lds_bytes(uint32_t L, uint32_t G, uint32_t Wr) { return 2u 
 // Workgroups of `threads` threads that can be resident at once for bands of
 // lds_bytes each and rows of Wr words (0 on error).
 uint32_t bands_capacity(uint32_t threads, uint32_t lds_bytes, bool general, uint32_t Wr);
-// One cooperative launch of G band workgroups of `threads` threads.
+// One cooperative launch of G band workgroups of `threads` threads. Sides
+// 512, 1024 and 2048, and 4096 with h != 0, keep their bands as bytes when
+// those fit (the fused kernels' word update), every other side as bits.
 hipError_t launch_bands(const BandArgs& a, uint32_t G, uint32_t threads, hipStream_t s);
 // Zero `words` tagged edge words (before tags restart from 0).
 hipError_t launch_bands_clear(uint64_t* pub, size_t words, hipStream_t s);

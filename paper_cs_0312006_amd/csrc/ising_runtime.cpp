@@ -466,6 +466,7 @@ static int sweep_bands(ising_ctx* ctx, uint64_t n, int64_t* ser, int64_t* part, 
     a.err = ctx->band_err;
     a.general = mode == 3u;
     a.bl = bits_lattice(ctx->table, L, a.Hw, mode);
+    a.at = ctx->table;
     for (uint64_t done = 0; done < n;) {
         const uint32_t m = (uint32_t)std::min<uint64_t>(n - done, chunk);
         if ((uint64_t)ctx->band_base + 2ull * m >= 0xffffffffull) {
