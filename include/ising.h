@@ -76,8 +76,9 @@ extern "C" {
 #define ISING_PLAN_GENERIC 4u   /* per-site draws; the only path for L % 8 != 0 */
 #define ISING_PLAN_FUSED_ROWS 5u /* as FUSED, a workgroup per band of whole rows (L/8 <= 16 * 64 * cw) */
 #define ISING_PLAN_BANDS 6u      /* the lattice split into bands of whole rows, one workgroup each, all
-                                   * resident at once; each band stays in LDS at one bit per site for
-                                   * every sweep of a launch, bands trade edge rows after each half-sweep
+                                   * resident at once; each band stays in LDS at one bit per site (as
+                                   * bytes at sides 512, 1024 and 2048, and 4096 with h != 0) for every
+                                   * sweep of a launch, bands trade edge rows after each half-sweep
                                    * (L % 8 == 0, L <= 16384) */
 /* Sweeps of one band-plan launch (the lattice crosses HBM once per launch);
  * longer calls are split into launches of this many sweeps. */
