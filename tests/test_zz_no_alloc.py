@@ -61,6 +61,7 @@ def test_static_sweeps_equal_ising_sweep(b):
         # 256 one-row bands: 256 pairs a sweep, launches of 256 sweeps
         (256, b.ISING_PLAN_BANDS, 0, 1, 1.0, 0.1, 2.0, 13, 600),
         (8192, b.ISING_PLAN_BANDS, 0, 32, -1.0, 0.05, 2.5, 14, 6),  # rows of two 64-word chunks
+        (2048, b.ISING_PLAN_BANDS, 0, 8, 1.0, 0.05, 2.269185, 15, 40),  # bands kept as bytes
     ]
     for L, plan, cw, rows, J, h, T, seed, n in cases:
         G.log(f"static scratch L={L} plan={plan}")
